@@ -1,0 +1,224 @@
+/*
+ * stencil.h - C ABI of the MI355X (gfx950) explicit stencil library.
+ *
+ * The library sweeps box and star stencils (d = 2 or 3, radius r, runtime
+ * weights) over dense grids on the GPU, fusing T time steps per pass.  Two
+ * kernel families compute the same operator:
+ *   VALU : T sequential steps per pass, intermediates kept on chip
+ *          (temporal fusion on general-purpose units);
+ *   MFMA : the T-step composite kernel applied once per pass as banded
+ *          (Toeplitz) matrix products on the matrix cores (kernel fusion),
+ *          paying the sparsity factor S and the fusion redundancy alpha.
+ * A host-side roofline model (paper, Sec. "Performance Formulation" and the
+ * four-scenario analysis) predicts which family wins.
+ *
+ * Step operator (paper, Introduction; Sec. "Original Stencil Problem"):
+ *     u'[x] = sum_{o in O} w[o] * ext(u)[x + o]
+ *   O_box  = [-r, r]^d,                      K = (2r+1)^d
+ *   O_star = {0} u {+-k e_i, 1 <= k <= r},   K = 2dr + 1
+ *   ext(u) = u inside the grid; outside: the constant halo value h
+ *            (Dirichlet, default 0) or the periodic image.
+ * A run of N steps returns step^N(in), whatever T, path or batching.
+ *
+ * Conventions shared by every entry point
+ *   - dims[] are slowest-first; grids are dense, contiguous, row-major, no
+ *     halo stored.  Element type is given by the plan's dtype.
+ *   - Weight vectors are float64 in canonical order:
+ *       box : row-major over (o_0..o_{d-1}) in [-r,r]^d, o_{d-1} fastest
+ *       star: centre, then axis 0 offsets -r..-1,+1..+r, then axis 1, ...
+ *   - Device pointers are HIP device addresses; `stream` is a hipStream_t
+ *     passed as void* (NULL = the default stream).
+ *   - Every function that can fail returns an int status (STENCIL_OK = 0);
+ *     stencil_last_error() gives a thread-local message for the last failure.
+ *     Argument validation happens before any HIP call.
+ */
+#ifndef STENCIL_MI355_H
+#define STENCIL_MI355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- enumerations -------------------------------------------------------- */
+enum stencil_shape { STENCIL_STAR = 0, STENCIL_BOX = 1 };
+
+/* Storage type of the grids.  STENCIL_F32_BF16X3 stores float32 and runs the
+ * MFMA path on bf16 hi/lo splits of data and weights (three products, lo*lo
+ * dropped) with float32 accumulation. */
+enum stencil_dtype {
+    STENCIL_F64 = 0,
+    STENCIL_F32 = 1,
+    STENCIL_BF16 = 2,
+    STENCIL_F16 = 3,
+    STENCIL_F32_BF16X3 = 4
+};
+
+enum stencil_boundary { STENCIL_DIRICHLET = 0, STENCIL_PERIODIC = 1 };
+
+enum stencil_path { STENCIL_PATH_AUTO = 0, STENCIL_PATH_VALU = 1, STENCIL_PATH_MFMA = 2 };
+
+enum stencil_status {
+    STENCIL_OK = 0,
+    STENCIL_ERR_INVALID_ARG = 1, /* bad shape/d/r/T/dims/weights/steps/pointer */
+    STENCIL_ERR_UNSUPPORTED = 2, /* dtype x path x (d, r, T) combination not built */
+    STENCIL_ERR_ALIAS = 3,       /* in and out overlap */
+    STENCIL_ERR_OOM = 4,         /* device or host allocation failed */
+    STENCIL_ERR_HIP = 5          /* a HIP runtime call failed (message holds it) */
+};
+
+/* Options of stencil_plan_set (value is a double). */
+enum stencil_option {
+    STENCIL_OPT_PATH = 1,       /* stencil_path; AUTO = model prediction      */
+    STENCIL_OPT_HALO_VALUE = 2, /* Dirichlet halo value h (default 0)         */
+    STENCIL_OPT_TILE_ROWS = 3,  /* VALU: rows streamed per workgroup (0=auto) */
+    STENCIL_OPT_T = 4           /* fusion depth T (>= 1)                      */
+};
+
+typedef struct stencil_plan_s *stencil_plan_t;
+
+/* ---- plan ---------------------------------------------------------------- */
+
+/* Read-only description of a plan. */
+typedef struct {
+    int shape, d, r, T, dtype, boundary;
+    int path;          /* resolved path: STENCIL_PATH_VALU or STENCIL_PATH_MFMA */
+    int64_t dims[3];
+    int K;             /* points of the single-step pattern                   */
+    int K_T;           /* non-zero points of the T-step composite kernel      */
+    double alpha;      /* fusion redundancy K_T / (T K) (MFMA path)           */
+    double S;          /* sparsity factor of the MFMA operand layout          */
+    double gamma;      /* products per useful MAC (3 for bf16x3, else 1)      */
+    double halo;       /* Dirichlet halo value                                */
+    int64_t workspace_bytes; /* device memory the plan owns                   */
+    double predicted_gst_valu;  /* model, GStencil/s                          */
+    double predicted_gst_mfma;
+    int predicted_winner;       /* -1 VALU, 0 tie, +1 MFMA                    */
+    int scenario;               /* 1..4 as in the paper's four scenarios      */
+} stencil_plan_info_t;
+
+/*
+ * Create a plan for `shape`, dimensionality d (2 or 3), radius r >= 1, K
+ * float64 weights (canonical order, copied: the caller may free them on
+ * return), dims[d] (each >= 1; periodic needs every dim >= 2*r*T + 1 on the
+ * MFMA path), fusion depth T >= 1, storage dtype and boundary.
+ * The plan owns a scratch grid for ping-pong passes and the MFMA operand
+ * blocks (size in workspace_bytes).  Path AUTO resolves to the model's
+ * predicted winner among the paths built for this combination.
+ * Errors: INVALID_ARG (d not in {2,3}, r < 1, T < 1, NULL or non-finite
+ * weights, dims < 1), UNSUPPORTED, OOM, HIP.  On error *plan is NULL.
+ */
+int stencil_plan(stencil_plan_t *plan, int shape, int d, int r, const double *weights,
+                 const int64_t *dims, int T, int dtype, int boundary);
+
+/* Change an option (see enum stencil_option) before the next run.  Changing
+ * PATH or T rebuilds the MFMA operand blocks.  Errors: INVALID_ARG,
+ * UNSUPPORTED, OOM, HIP. */
+int stencil_plan_set(stencil_plan_t plan, int option, double value);
+
+/* Fill *out.  Errors: INVALID_ARG (NULL). */
+int stencil_plan_info(stencil_plan_t plan, stencil_plan_info_t *out);
+
+/*
+ * out = step^steps(in) on `stream`.  `in` and `out` are device pointers to
+ * dense grids of the plan's dims and dtype.  `in` is never written; `out` is
+ * fully overwritten.  steps = 0 copies in to out.  The work is asynchronous;
+ * kernel faults surface at stream synchronisation.  One run per plan may be
+ * in flight (the plan's scratch grid is shared).
+ * Passes: floor(steps / T) passes of T steps plus one pass of steps mod T.
+ * Errors: INVALID_ARG (NULL pointers, steps < 0), ALIAS (in/out overlap),
+ * HIP (launch failure).
+ */
+int stencil_run(stencil_plan_t plan, const void *in, void *out, int64_t steps, void *stream);
+
+/*
+ * Run n independent jobs (plans[i], ins[i] -> outs[i], steps[i] steps) as
+ * batched launches on one stream: each round issues one pass of every job
+ * that still has steps left, grouped by kernel variant, each group in a
+ * single persistent launch whose workgroups pull tiles of all its jobs from
+ * one work list.  Results equal stencil_run of each job alone, bit for bit.
+ * Plans may not repeat within one call.  Errors as stencil_run; on an
+ * argument error no job is started.
+ */
+int stencil_run_batch(int n, const stencil_plan_t *plans, const void *const *ins,
+                      void *const *outs, const int64_t *steps, void *stream);
+
+/* Release a plan and its device memory.  Call only after the stream that ran
+ * it has drained.  NULL is ignored. */
+void stencil_plan_destroy(stencil_plan_t plan);
+
+/* Thread-local message of the last failure of this thread ("" if none). */
+const char *stencil_last_error(void);
+
+/* ---- host-only helpers (no GPU needed) ----------------------------------- */
+
+/*
+ * T-step composite kernel of kernel fusion (paper, Sec. "Handling Stencils
+ * with Small Radius"): the T-fold full convolution of the weight pattern with
+ * itself, radius R = r*T, written dense as (2R+1)^d float64 values indexed
+ * by offset + R (row-major, last axis fastest) into out (caller-allocated).
+ * Returns the number of non-zero displacements (K_T) in *k_t if non-NULL.
+ * Errors: INVALID_ARG.
+ */
+int stencil_compose(int shape, int d, int r, const double *weights, int T, double *out,
+                    int *k_t);
+
+/* Hardware ceilings of the roofline model (flop/s, bytes/s). */
+typedef struct {
+    double BB;           /* memory bandwidth                                   */
+    double PP_valu;      /* peak of the instructions the VALU path issues      */
+    double PP_mfma;      /* dense matrix-core peak for the MFMA path's type    */
+    double PP_mfma_sparse; /* 2:4 structured-sparse matrix-core peak           */
+} stencil_hw_t;
+
+/* MI355X datasheet ceilings for dtype's arithmetic (VALU without packed
+ * FP32; MFMA dense; HBM3E 8 TB/s).  Errors: INVALID_ARG. */
+int stencil_hw_default(int dtype, stencil_hw_t *out);
+
+typedef struct {
+    int shape, d, r, T;
+    int dtype;       /* selects D (bytes per stored element) and gamma        */
+    double S;        /* sparsity factor; <= 0 means: this library's layout    */
+    double alpha;    /* redundancy factor; <= 0 means: K_T / (T K)            */
+    int sparse;      /* 1: use PP_mfma_sparse for the matrix side             */
+} stencil_model_in_t;
+
+typedef struct {
+    int K, K_T;
+    double D, alpha, S, gamma;
+    double C_valu;       /* flops per point per pass, VALU: 2 K T             */
+    double C_mfma;       /* executed flops per point per pass: gamma alpha/S 2KT */
+    double M;            /* bytes per point per pass: 2 D                     */
+    double I_valu, I_mfma;
+    double ridge_valu, ridge_mfma;
+    double P_valu;       /* attainable useful flop/s, VALU                    */
+    double P_mfma_raw;   /* attainable executed flop/s, MFMA                  */
+    double P_mfma;       /* attainable useful flop/s, MFMA (raw * S/(gamma alpha)) */
+    double gst_valu, gst_mfma; /* GStencil/s = point-steps / s / 1e9         */
+    double ratio;        /* gst_mfma / gst_valu                               */
+    int scenario;        /* 1 MB->MB, 2 MB->CB, 3 CB->MB, 4 CB->CB            */
+    int sweet_spot;      /* alpha*gamma < S PP_mfma / PP_valu                 */
+    int winner;          /* -1 VALU, 0 tie (ratio in [0.87, 1.15]), +1 MFMA    */
+} stencil_model_out_t;
+
+/*
+ * Roofline prediction for both paths (paper, Sec. "Performance Formulation":
+ * roofline, CUDA-core temporal fusion, Tensor-Core kernel fusion with S and
+ * alpha; Sec. "Performance Comparative Analysis": speed-up ratio, four
+ * scenarios, sweet spot; sparse units keep I and raise the peak).
+ * hw NULL = stencil_hw_default(in->dtype).  Errors: INVALID_ARG.
+ */
+int stencil_model_predict(const stencil_model_in_t *in, const stencil_hw_t *hw,
+                          stencil_model_out_t *out);
+
+/* Sparsity factor S of this library's MFMA operand layout for the T-step
+ * composite of (shape, d, r) in dtype: useful MACs / executed MACs.
+ * Returns a value in (0, 1], or a negative value on invalid arguments. */
+double stencil_mfma_sparsity(int shape, int d, int r, int T, int dtype);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_MI355_H */

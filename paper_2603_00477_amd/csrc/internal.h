@@ -1,0 +1,113 @@
+// Internal declarations of the stencil library (host side and kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+
+namespace stl {
+
+constexpr int kMaxD = 3;
+constexpr int kMaxK = 512;  // single-step points handled by the kernels' weight arrays
+
+// Record a message for stencil_last_error() and return `code`.
+int fail(int code, const std::string &msg);
+
+// Bytes per stored element of a dtype (bf16x3 stores float32).
+int dtype_bytes(int dtype);
+
+// Canonical offsets of the pattern; returns K (or -1).
+int pattern_offsets(int shape, int d, int r, std::vector<int> *offs);
+
+// Dense composite kernel of T steps, (2rT+1)^d values indexed by offset+rT.
+void compose_dense(int shape, int d, int r, const double *w, int T, std::vector<double> *out);
+
+// Arguments of one pass of one job, as the launchers take them.
+struct PassArgs {
+    const void *src;
+    void *dst;
+    int64_t dims[kMaxD];
+    int d;
+    int region_lo[kMaxD];    // output box [lo, hi) written by this launch
+    int region_hi[kMaxD];
+    int boundary;
+    double halo;
+    int steps;               // steps fused in this pass (1..T)
+    const double *w;         // K single-step weights, canonical order (host memory)
+    const int *offs;         // K x d offsets, canonical order (host memory)
+    int K;
+    int tile_rows;           // VALU rows per workgroup (0 = auto)
+    const void *afrag;       // MFMA operand fragments (device memory)
+    const void *afrag_lo;    // compensated mode: lo parts
+    int R;                   // MFMA composite radius (r * steps)
+    int num_cu;
+};
+
+// One launchable kernel variant.
+struct KernelEntry {
+    int path;    // STENCIL_PATH_VALU or STENCIL_PATH_MFMA
+    int dtype;
+    int shape;   // -1 = any
+    int d;
+    int r;       // -1 = any
+    int t;       // steps per pass, -1 = any
+    hipError_t (*launch)(const PassArgs &, hipStream_t);
+};
+
+// Kernel registries, one per source file.
+const std::vector<KernelEntry> &valu2d_kernels();
+const std::vector<KernelEntry> &valu3d_kernels();
+const std::vector<KernelEntry> &generic_kernels();
+const std::vector<KernelEntry> &mfma2d_kernels();
+const std::vector<KernelEntry> &mfma3d_kernels();
+
+const KernelEntry *find_kernel(int path, int dtype, int shape, int d, int r, int t);
+
+// MFMA operand fragments for the composite of `steps` steps.
+struct MfmaLayout {
+    int R;       // composite radius
+    int kdim;    // k of the MFMA instruction
+    int Kp;      // padded band length (multiple of kdim)
+    int nblk;    // Kp / kdim
+    double S;    // useful / executed MACs of this layout
+};
+MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype);
+
+// Build the lane-ordered operand fragments of the composite on the host.
+// `hi`/`lo` receive raw element bytes in the MFMA operand type.
+void mfma_build_fragments(int shape, int d, int r, const double *w, int steps, int dtype,
+                          std::vector<uint8_t> *hi, std::vector<uint8_t> *lo);
+
+int device_cu_count();
+
+}  // namespace stl
+
+struct stencil_plan_s {
+    int shape, d, r, T, dtype, boundary;
+    int path_req;   // requested (may be AUTO)
+    int path;       // resolved
+    int64_t dims[stl::kMaxD];
+    int64_t npts;
+    int K;
+    std::vector<int> offs;
+    std::vector<double> w;      // canonical single-step weights
+    double halo;
+    int tile_rows;
+    // model results
+    int K_T;
+    double alpha, S, gamma;
+    double pred_valu, pred_mfma;
+    int pred_winner, scenario;
+    // device resources
+    int device;
+    void *scratch;
+    size_t scratch_bytes;
+    // MFMA fragments per pass depth (index = steps in pass, 1..T)
+    std::vector<void *> afrag;
+    std::vector<void *> afrag_lo;
+    size_t afrag_bytes;
+};

@@ -1,0 +1,308 @@
+// VALU path, d = 2: T explicit steps fused per pass (temporal fusion on the
+// vector units; paper, Sec. "CUDA Core Implementation with Temporal Fusion":
+// C grows by t, M stays 2D per point because intermediates stay on chip).
+//
+// Work decomposition
+//   A workgroup of NT threads owns a column band of NC = NT*W columns (each
+//   thread W consecutive columns) and streams down a segment of rows.  Of the
+//   NC columns, E = roundup(R*T, W) on each side are the skirt that later steps
+//   consume; the band's valid output width is BX = NC - 2E.
+//
+// Step pipeline (one barrier per row)
+//   Stage 0 loads input row k (prefetched U rows ahead into registers) and
+//   writes it to an LDS row buffer.  Stage s = 1..T reads the row that stage
+//   s-1 wrote one iteration earlier (double-buffered by iteration parity),
+//   scatters it into 2R+1 rotating accumulator rows per thread column
+//   (input-stationary: input row i adds w[a][.] to output row i-a), and emits
+//   the completed output row i-R: to LDS for the next stage, or to HBM for
+//   stage T.  Contributions to an output arrive in canonical order (kernel row
+//   a ascending, column b ascending).
+//
+// Boundaries
+//   Dirichlet: every field, intermediate ones included, is h outside the grid
+//   (rows and columns outside are forced to h after each stage).  Periodic:
+//   loads wrap; intermediate values in the skirt are then the periodic images.
+//
+// The kernel writes an arbitrary output rectangle [oy0,oy1) x [ox0,ox1), used
+// both for whole grids and for the Dirichlet boundary band of the MFMA path.
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "valu_common.h"
+
+namespace stl {
+namespace {
+
+template <typename TC, int K>
+struct Valu2DArgs {
+    const void *src;
+    void *dst;
+    int n0, n1;
+    int oy0, oy1, ox0, ox1;
+    int BX, BY, nbands, nsegs, ntiles;
+    int periodic;
+    TC h;
+    TC w[K];
+};
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
+struct Valu2DCfg {
+    static constexpr int K = SHAPE == STENCIL_BOX ? (2 * R + 1) * (2 * R + 1) : 4 * R + 1;
+    static constexpr int NC = NT * W;
+    static constexpr int E = ((R * T + W - 1) / W) * W;
+    static constexpr int PADL = ((R + W - 1) / W) * W;
+    static constexpr int LROW = NC + 2 * PADL;
+    static constexpr int Q = 2 * R + 1;
+    // rows prefetched ahead: a multiple of Q, at least 4
+    static constexpr int U = Q * ((4 + Q - 1) / Q);
+};
+
+template <int SHAPE, int R>
+__device__ __forceinline__ int star_axis_index(int axis, int off)
+{
+    // canonical star order: centre, axis0 -R..-1,+1..+R, axis1 ...
+    return 1 + axis * 2 * R + (off < 0 ? off + R : off + R - 1);
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
+__global__ __launch_bounds__(NT) void valu2d_kernel(
+    Valu2DArgs<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K> a)
+{
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
+    constexpr int Q = Cfg::Q;
+    constexpr int U = Cfg::U;
+    constexpr int LROW = Cfg::LROW;
+    constexpr int PADL = Cfg::PADL;
+    using Vec = RawVec<TS, W>;
+
+    __shared__ TC lds[T][2][LROW];
+
+    const int tid = threadIdx.x;
+    // XCD-aware tile order: blocks that land on one XCD take consecutive tiles
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    const int band = tile / a.nsegs;
+    const int seg = tile - band * a.nsegs;
+    const int x0 = a.ox0 + band * a.BX;
+    const int y0 = a.oy0 + seg * a.BY;
+    const int y1 = min(y0 + a.BY, a.oy1);
+    const int BYe = y1 - y0;
+    const int xe = min(x0 + a.BX, a.ox1);
+    const int cb = x0 - Cfg::E + tid * W;  // first column owned by this thread
+
+    const TS *src = static_cast<const TS *>(a.src);
+    TS *dst = static_cast<TS *>(a.dst);
+    const int n0 = a.n0, n1 = a.n1;
+    const bool periodic = a.periodic != 0;
+    const TC h = a.h;
+
+    // zero the LDS pads once (never written afterwards)
+    for (int i = tid; i < T * 2 * LROW; i += NT) (&lds[0][0][0])[i] = TC(0);
+
+    // per-column facts
+    bool col_in[W];
+    int col_src[W];
+    bool col_store[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const int c = cb + j;
+        col_in[j] = c >= 0 && c < n1;
+        col_src[j] = periodic ? wrap(c, n1) : c;
+        col_store[j] = c >= x0 && c < xe;
+    }
+    const bool vec_ok = vec_aligned<TS, W>(src, n1, cb) && cb >= 0 && cb + W <= n1;
+    const TS hs = to_storage<TS>(h);
+
+    const int KTOT = BYe + 2 * R * T + T;
+    const int ybase = y0 - R * T;
+
+    // accumulators: T stages x Q rotating rows x W columns
+    TC acc[T][Q][W];
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc[s][q][j] = TC(0);
+
+    auto load_row = [&](int k, Vec &v) {
+        const int i = ybase + k;
+        const bool row_in = i >= 0 && i < n0;
+        if (!periodic && !row_in) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) v.e[j] = hs;
+            return;
+        }
+        const int ri = periodic ? wrap(i, n0) : i;
+        const TS *rowp = src + (int64_t)ri * n1;
+        if (vec_ok) {
+            v.load(rowp + cb);
+        } else {
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                v.e[j] = (periodic || col_in[j]) ? rowp[col_src[j]] : hs;
+        }
+    };
+
+    Vec ring[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (u < KTOT) load_row(u, ring[u]);
+    __syncthreads();
+
+    for (int kb = 0; kb < KTOT; kb += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = kb + u;
+            if (k >= KTOT) break;
+            const int par = k & 1;
+            // ---- stage 0: input row -> LDS, prefetch U rows ahead
+            {
+                TC *w0 = &lds[0][par][PADL + tid * W];
+#pragma unroll
+                for (int j = 0; j < W; ++j) w0[j] = to_compute<TC>(ring[u].e[j]);
+                if (k + U < KTOT) load_row(k + U, ring[u]);
+            }
+            // ---- stages 1..T
+#pragma unroll
+            for (int s = 1; s <= T; ++s) {
+                const bool active = k >= s + 2 * R * (s - 1) && k < BYe + 2 * R * T + s;
+                const int qc = u % Q;  // slot completing at this iteration
+                if (active) {
+                    const TC *rb = &lds[s - 1][par ^ 1][PADL - R + tid * W];
+                    TC win[W + 2 * R];
+#pragma unroll
+                    for (int j = 0; j < W + 2 * R; ++j) win[j] = rb[j];
+#pragma unroll
+                    for (int ao = -R; ao <= R; ++ao) {
+                        const int q = ((u - ao + R) % Q + Q) % Q;
+                        if (SHAPE == STENCIL_BOX) {
+#pragma unroll
+                            for (int bo = -R; bo <= R; ++bo) {
+                                const TC wv = a.w[(ao + R) * (2 * R + 1) + (bo + R)];
+#pragma unroll
+                                for (int j = 0; j < W; ++j)
+                                    acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
+                            }
+                        } else {
+                            if (ao != 0) {
+                                const TC wv = a.w[star_axis_index<SHAPE, R>(0, ao)];
+#pragma unroll
+                                for (int j = 0; j < W; ++j)
+                                    acc[s - 1][q][j] = fma_c(wv, win[j + R], acc[s - 1][q][j]);
+                            } else {
+#pragma unroll
+                                for (int bo = -R; bo <= R; ++bo) {
+                                    const TC wv = bo == 0 ? a.w[0]
+                                                          : a.w[star_axis_index<SHAPE, R>(1, bo)];
+#pragma unroll
+                                    for (int j = 0; j < W; ++j)
+                                        acc[s - 1][q][j] =
+                                            fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
+                                }
+                            }
+                        }
+                    }
+                    // emit the completed row
+                    const int yo = ybase + k - s * (1 + R);  // row completed by stage s
+                    TC outv[W];
+#pragma unroll
+                    for (int j = 0; j < W; ++j) outv[j] = acc[s - 1][qc][j];
+                    if (s < T) {
+                        if (!periodic) {
+                            const bool row_in = yo >= 0 && yo < n0;
+#pragma unroll
+                            for (int j = 0; j < W; ++j)
+                                if (!(row_in && col_in[j])) outv[j] = h;
+                        }
+                        TC *wr = &lds[s][par][PADL + tid * W];
+#pragma unroll
+                        for (int j = 0; j < W; ++j) wr[j] = outv[j];
+                    } else if (yo >= y0 && yo < y1) {
+                        TS *rowp = dst + (int64_t)yo * n1;
+                        Vec ov;
+#pragma unroll
+                        for (int j = 0; j < W; ++j) ov.e[j] = to_storage<TS>(outv[j]);
+                        bool all = vec_ok;
+#pragma unroll
+                        for (int j = 0; j < W; ++j) all = all && col_store[j];
+                        if (all) {
+                            ov.store(rowp + cb);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < W; ++j)
+                                if (col_store[j]) rowp[cb + j] = ov.e[j];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc[s - 1][qc][j] = TC(0);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T>
+hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
+{
+    constexpr int W = 16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS);
+    constexpr int NT = 256;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
+    Valu2DArgs<TC, Cfg::K> a;
+    a.src = p.src;
+    a.dst = p.dst;
+    a.n0 = (int)p.dims[0];
+    a.n1 = (int)p.dims[1];
+    a.oy0 = p.region_lo[0];
+    a.oy1 = p.region_hi[0];
+    a.ox0 = p.region_lo[1];
+    a.ox1 = p.region_hi[1];
+    a.periodic = p.boundary == STENCIL_PERIODIC;
+    a.h = (TC)p.halo;
+    for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
+    a.BX = Cfg::NC - 2 * Cfg::E;
+    if (a.BX <= 0) return hipErrorInvalidValue;
+    const int W_out = a.ox1 - a.ox0, H_out = a.oy1 - a.oy0;
+    if (W_out <= 0 || H_out <= 0) return hipSuccess;
+    a.nbands = (W_out + a.BX - 1) / a.BX;
+    // rows per workgroup: enough tiles to fill the chip several times over
+    int BY = p.tile_rows;
+    if (BY <= 0) {
+        const int target = 8 * (p.num_cu > 0 ? p.num_cu : 256);
+        const int segs = (target + a.nbands - 1) / a.nbands;
+        BY = (H_out + segs - 1) / segs;
+        const int minBY = 8 * R * T > 64 ? 8 * R * T : 64;
+        if (BY < minBY) BY = minBY;
+        if (BY > 1024) BY = 1024;
+    }
+    a.BY = BY;
+    a.nsegs = (H_out + BY - 1) / BY;
+    a.ntiles = a.nbands * a.nsegs;
+    hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, W, NT>), dim3(a.ntiles), dim3(NT), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+#define V2(TS, TC, DT, SH, R, T) \
+    {STENCIL_PATH_VALU, DT, SH, 2, R, T, &launch_valu2d<TS, TC, SH, R, T>}
+#define V2_T(TS, TC, DT, SH, R) \
+    V2(TS, TC, DT, SH, R, 1), V2(TS, TC, DT, SH, R, 2), V2(TS, TC, DT, SH, R, 3), V2(TS, TC, DT, SH, R, 4)
+#define V2_R(TS, TC, DT, SH) V2_T(TS, TC, DT, SH, 1), V2_T(TS, TC, DT, SH, 2), V2_T(TS, TC, DT, SH, 3)
+#define V2_S(TS, TC, DT) V2_R(TS, TC, DT, STENCIL_STAR), V2_R(TS, TC, DT, STENCIL_BOX)
+
+}  // namespace
+
+const std::vector<KernelEntry> &valu2d_kernels()
+{
+    static const std::vector<KernelEntry> table = {
+        V2_S(double, double, STENCIL_F64),
+        V2_S(float, float, STENCIL_F32),
+    };
+    return table;
+}
+
+}  // namespace stl

@@ -1,0 +1,111 @@
+"""GPU parity of the VALU path (temporal fusion) against the FP64 oracle.
+
+Sizes span several workgroup bands and row segments with ragged tails; steps
+are chosen so that the last pass has fewer than T steps.  Tolerances: FP64
+relative max-norm error <= 1e-12, FP32 <= 1e-5 (inputs rounded to float32,
+error measured against the oracle on the original float64 data)."""
+import numpy as np
+import pytest
+
+import stencil_inputs as si
+from gpu_util import case_inputs, oracle, rel_inf, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def stl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_00477_amd as stl
+    stl.lib()
+    return stl
+
+
+def test_config1_star2d1r_jacobi(stl):
+    """Star-2D1R, weights 0.2, 512x512 FP64, U[0,1) seed 1001, zero Dirichlet
+    halo, 10 steps, T = 1."""
+    u0 = si.uniform_grid((512, 512), seed=si.data_seed(1, 1))
+    w = np.full(5, 0.2)
+    p = stl.Plan("star", 2, 1, w, (512, 512), T=1, dtype="f64", path="valu")
+    got = run_gpu(p, si.round_to(u0, "f64")[1], 10)
+    ref = oracle("star", 2, 1, w, u0, 10, "dirichlet")
+    assert rel_inf(got, ref) <= 1e-12
+
+
+CASES = [(shape, r, T, dt) for shape in ("star", "box") for r in (1, 2, 3) for T in (1, 2, 3, 4)
+         for dt in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("shape,r,T,dt", CASES)
+def test_valu2d_dirichlet(stl, shape, r, T, dt):
+    dims = (301, 1213)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=2000 + 10 * r + T)
+    steps = 2 * T + 1
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="valu", halo=0.25)
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0, steps, "dirichlet", 0.25)
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("shape,r,T,dt", [c for c in CASES if c[2] in (1, 3, 4)])
+def test_valu2d_periodic(stl, shape, r, T, dt):
+    dims = (157, 1100)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=3000 + 10 * r + T)
+    steps = T + 2
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, boundary="periodic", path="valu")
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0, steps, "periodic")
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dims", [(1, 1), (1, 7), (9, 1), (5, 3), (33, 2049), (2, 513)])
+def test_valu2d_small_and_thin(stl, dims):
+    for boundary in ("dirichlet", "periodic"):
+        u0, u0r, t, w = case_inputs("box", 2, 2, dims, "f64", seed=4000)
+        p = stl.Plan("box", 2, 2, w, dims, T=3, dtype="f64", path="valu", boundary=boundary)
+        got = run_gpu(p, t, 7)
+        ref = oracle("box", 2, 2, w, u0, 7, boundary)
+        assert rel_inf(got, ref) <= 1e-12, (dims, boundary)
+
+
+def test_valu2d_t_fusion_consistent(stl):
+    """T-fused passes equal single-step passes (both against the oracle and
+    against each other)."""
+    dims = (400, 900)
+    u0, u0r, t, w = case_inputs("box", 2, 3, dims, "f64", seed=4100)
+    outs = []
+    for T in (1, 2, 4):
+        p = stl.Plan("box", 2, 3, w, dims, T=T, dtype="f64", path="valu")
+        outs.append(run_gpu(p, t, 8))
+    ref = oracle("box", 2, 3, w, u0, 8, "dirichlet")
+    for o in outs:
+        assert rel_inf(o, ref) <= 1e-12
+    assert rel_inf(outs[0], outs[2]) <= 1e-13
+
+
+def test_steps_zero_copies(stl):
+    import torch
+    dims = (64, 80)
+    u0, u0r, t, w = case_inputs("star", 2, 1, dims, "f32", seed=4200)
+    p = stl.Plan("star", 2, 1, w, dims, T=2, dtype="f32")
+    got = run_gpu(p, t, 0)
+    assert np.array_equal(got, u0r)
+
+
+def test_in_not_modified_and_alias_rejected(stl):
+    import torch
+    dims = (128, 256)
+    u0, u0r, t, w = case_inputs("box", 2, 1, dims, "f64", seed=4300)
+    p = stl.Plan("box", 2, 1, w, dims, T=2, dtype="f64")
+    x = t.cuda()
+    y = torch.empty_like(x)
+    p.run(x, y, 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), u0r)
+    with pytest.raises(stl.StencilError) as e:
+        p.run(x, x, 3)
+    assert e.value.status == "ALIAS"
