@@ -16,7 +16,7 @@
 namespace stl {
 namespace {
 
-constexpr int kGenericMaxK = 128;
+constexpr int kGenericMaxK = 343;  // box r = 3 in 3D; the argument block stays under 4 KiB
 
 template <typename TC>
 struct GenericArgs {

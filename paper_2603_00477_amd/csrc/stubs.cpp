@@ -2,11 +2,6 @@
 #include "internal.h"
 
 namespace stl {
-const std::vector<KernelEntry> &valu3d_kernels()
-{
-    static const std::vector<KernelEntry> t;
-    return t;
-}
 const std::vector<KernelEntry> &mfma2d_kernels()
 {
     static const std::vector<KernelEntry> t;

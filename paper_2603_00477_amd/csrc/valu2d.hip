@@ -116,6 +116,16 @@ __global__ __launch_bounds__(NT) void valu2d_kernel(
     const bool vec_ok = vec_aligned<TS, W>(src, n1, cb) && cb >= 0 && cb + W <= n1;
     const TS hs = to_storage<TS>(h);
 
+    // Weights: scalar registers hold up to ~48 dwords of them; larger sets
+    // (49 float64 box weights) are pinned in vector registers, otherwise the
+    // compiler spills them to vector lanes and pays a readlane per use.
+    TC wk[Cfg::K];
+#pragma unroll
+    for (int k = 0; k < Cfg::K; ++k) {
+        wk[k] = a.w[k];
+        if constexpr (sizeof(TC) * Cfg::K > 192) asm volatile("" : "+v"(wk[k]));
+    }
+
     const int KTOT = BYe + 2 * R * T + T;
     const int ybase = y0 - R * T;
 
@@ -182,22 +192,22 @@ __global__ __launch_bounds__(NT) void valu2d_kernel(
                         if (SHAPE == STENCIL_BOX) {
 #pragma unroll
                             for (int bo = -R; bo <= R; ++bo) {
-                                const TC wv = a.w[(ao + R) * (2 * R + 1) + (bo + R)];
+                                const TC wv = wk[(ao + R) * (2 * R + 1) + (bo + R)];
 #pragma unroll
                                 for (int j = 0; j < W; ++j)
                                     acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
                             }
                         } else {
                             if (ao != 0) {
-                                const TC wv = a.w[star_axis_index<SHAPE, R>(0, ao)];
+                                const TC wv = wk[star_axis_index<SHAPE, R>(0, ao)];
 #pragma unroll
                                 for (int j = 0; j < W; ++j)
                                     acc[s - 1][q][j] = fma_c(wv, win[j + R], acc[s - 1][q][j]);
                             } else {
 #pragma unroll
                                 for (int bo = -R; bo <= R; ++bo) {
-                                    const TC wv = bo == 0 ? a.w[0]
-                                                          : a.w[star_axis_index<SHAPE, R>(1, bo)];
+                                    const TC wv = bo == 0 ? wk[0]
+                                                          : wk[star_axis_index<SHAPE, R>(1, bo)];
 #pragma unroll
                                     for (int j = 0; j < W; ++j)
                                         acc[s - 1][q][j] =

@@ -1,0 +1,386 @@
+// VALU path, d = 3: T explicit steps fused per pass, streaming along z (the
+// slowest axis).
+//
+// A workgroup of TX x TY threads owns an extended in-plane tile of
+// (TY*WY) x (TX*W) points (each thread WY rows x W consecutive columns) and
+// streams down a segment of planes.  The tile carries a skirt of R*T points on
+// every side for the later steps; the valid output tile is the interior.
+// The step pipeline is the one of the 2D kernel with rows replaced by planes:
+// stage 0 writes input plane k to an LDS plane buffer; stage s reads the plane
+// stage s-1 wrote one iteration earlier, scatters it into 2R+1 rotating
+// accumulator planes (input plane z adds its in-plane neighbourhood weighted
+// by w[c][.][.] to output plane z-c) and emits the completed plane.  One
+// barrier per plane.
+//
+// Weights: a set of up to 48 dwords lives in scalar registers, up to 64
+// dwords is pinned in vector registers, larger sets (box r >= 2) are read from
+// LDS with uniform addresses.
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "valu_common.h"
+
+namespace stl {
+namespace {
+
+template <typename TC, int K>
+struct Valu3DArgs {
+    const void *src;
+    void *dst;
+    int n0, n1, n2;
+    int oz0, oz1, oy0, oy1, ox0, ox1;
+    int BZ, BYv, BXv, nty, ntx, nzs, ntiles;
+    int periodic;
+    TC h;
+    TC w[K];
+};
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+struct Valu3DCfg {
+    static constexpr int K = SHAPE == STENCIL_BOX ? (2 * R + 1) * (2 * R + 1) * (2 * R + 1) : 6 * R + 1;
+    static constexpr int NT = TX * TY;
+    static constexpr int PY = TY * WY;                      // extended rows
+    static constexpr int PX = TX * W;                       // extended columns
+    static constexpr int EY = R * T;                        // row skirt
+    static constexpr int EX = ((R * T + W - 1) / W) * W;    // column skirt (vector aligned)
+    static constexpr int PADX = ((R + W - 1) / W) * W;      // LDS column pad
+    static constexpr int LDX = PX + 2 * PADX;               // LDS row pitch
+    static constexpr int LROWS = PY + 2 * R;                // LDS rows (R pad each side)
+    static constexpr int PLANE = LROWS * LDX;
+    static constexpr int Q = 2 * R + 1;
+    static constexpr int U = Q;                             // planes prefetched ahead
+    static constexpr int WMODE = sizeof(TC) * K <= 192 ? 0 : (sizeof(TC) * K <= 256 ? 1 : 2);
+};
+
+template <int R>
+__device__ __forceinline__ int star3_index(int axis, int off)
+{
+    return 1 + axis * 2 * R + (off < 0 ? off + R : off + R - 1);
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void valu3d_kernel(
+    Valu3DArgs<TC, Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> a)
+{
+    using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    constexpr int K = Cfg::K;
+    constexpr int Q = Cfg::Q;
+    constexpr int U = Cfg::U;
+    constexpr int NT = Cfg::NT;
+    constexpr int LDX = Cfg::LDX;
+    constexpr int PLANE = Cfg::PLANE;
+    constexpr int PADX = Cfg::PADX;
+    constexpr int WMODE = Cfg::WMODE;
+    using Vec = RawVec<TS, W>;
+
+    __shared__ TC lds[T][2][PLANE];
+    __shared__ TC wl[WMODE == 2 ? K : 1];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    const int tzs = tile / (a.nty * a.ntx);
+    const int rem = tile - tzs * (a.nty * a.ntx);
+    const int tyi = rem / a.ntx, txi = rem - tyi * a.ntx;
+    const int z0 = a.oz0 + tzs * a.BZ;
+    const int z1 = min(z0 + a.BZ, a.oz1);
+    const int BZe = z1 - z0;
+    const int y0 = a.oy0 + tyi * a.BYv;
+    const int ye = min(y0 + a.BYv, a.oy1);
+    const int x0 = a.ox0 + txi * a.BXv;
+    const int xe = min(x0 + a.BXv, a.ox1);
+    const int cy0 = y0 - Cfg::EY + ty * WY;  // first row of this thread
+    const int cx0 = x0 - Cfg::EX + tx * W;   // first column of this thread
+
+    const TS *src = static_cast<const TS *>(a.src);
+    TS *dst = static_cast<TS *>(a.dst);
+    const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+    const bool periodic = a.periodic != 0;
+    const TC h = a.h;
+    const TS hs = to_storage<TS>(h);
+
+    for (int i = tid; i < T * 2 * PLANE; i += NT) (&lds[0][0][0])[i] = TC(0);
+    if constexpr (WMODE == 2)
+        for (int i = tid; i < K; i += NT) wl[i] = a.w[i];
+
+    TC wk[WMODE == 2 ? 1 : K];
+    if constexpr (WMODE != 2) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            wk[k] = a.w[k];
+            if constexpr (WMODE == 1) asm volatile("" : "+v"(wk[k]));
+        }
+    }
+    auto weight = [&](int k) -> TC {
+        if constexpr (WMODE == 2) return wl[k];
+        else return wk[k];
+    };
+
+    bool col_in[W], col_store[W];
+    int col_src[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const int c = cx0 + j;
+        col_in[j] = c >= 0 && c < n2;
+        col_src[j] = periodic ? wrap(c, n2) : c;
+        col_store[j] = c >= x0 && c < xe;
+    }
+    bool row_in[WY], row_store[WY];
+    int row_src[WY];
+#pragma unroll
+    for (int i = 0; i < WY; ++i) {
+        const int r = cy0 + i;
+        row_in[i] = r >= 0 && r < n1;
+        row_src[i] = periodic ? wrap(r, n1) : r;
+        row_store[i] = r >= y0 && r < ye;
+    }
+    const bool vec_ok = vec_aligned<TS, W>(src, n2, cx0) && cx0 >= 0 && cx0 + W <= n2;
+
+    const int KTOT = BZe + 2 * R * T + T;
+    const int zbase = z0 - R * T;
+
+    TC acc[T][Q][WY][W];
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int i = 0; i < WY; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc[s][q][i][j] = TC(0);
+
+    auto load_plane = [&](int k, Vec *v) {
+        const int z = zbase + k;
+        const bool zin = z >= 0 && z < n0;
+        if (!periodic && !zin) {
+#pragma unroll
+            for (int i = 0; i < WY; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j) v[i].e[j] = hs;
+            return;
+        }
+        const TS *pl = src + (int64_t)(periodic ? wrap(z, n0) : z) * n1 * n2;
+#pragma unroll
+        for (int i = 0; i < WY; ++i) {
+            if (!periodic && !row_in[i]) {
+#pragma unroll
+                for (int j = 0; j < W; ++j) v[i].e[j] = hs;
+                continue;
+            }
+            const TS *rowp = pl + (int64_t)row_src[i] * n2;
+            if (vec_ok) {
+                v[i].load(rowp + cx0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < W; ++j)
+                    v[i].e[j] = (periodic || col_in[j]) ? rowp[col_src[j]] : hs;
+            }
+        }
+    };
+
+    Vec ring[U][WY];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (u < KTOT) load_plane(u, ring[u]);
+    __syncthreads();
+
+    // LDS position of this thread's first point inside a plane buffer
+    const int lpos = (R + ty * WY) * LDX + PADX + tx * W;
+
+    for (int kb = 0; kb < KTOT; kb += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = kb + u;
+            if (k >= KTOT) break;
+            const int par = k & 1;
+            {
+                TC *w0 = &lds[0][par][lpos];
+#pragma unroll
+                for (int i = 0; i < WY; ++i)
+#pragma unroll
+                    for (int j = 0; j < W; ++j) w0[i * LDX + j] = to_compute<TC>(ring[u][i].e[j]);
+                if (k + U < KTOT) load_plane(k + U, ring[u]);
+            }
+#pragma unroll
+            for (int s = 1; s <= T; ++s) {
+                const bool active = k >= s + 2 * R * (s - 1) && k < BZe + 2 * R * T + s;
+                const int qc = u % Q;
+                if (active) {
+                    if constexpr (WMODE == 2) asm volatile("" ::: "memory");
+                    const TC *rb = &lds[s - 1][par ^ 1][lpos - R * LDX - R];
+                    // stream the (WY+2R) x (W+2R) neighbourhood one LDS row at a time
+#pragma unroll
+                    for (int wi = 0; wi < WY + 2 * R; ++wi) {
+                        const bool mid = wi >= R && wi < R + WY;  // row holds an output row
+                        TC row[W + 2 * R];
+#pragma unroll
+                        for (int j = 0; j < W + 2 * R; ++j) {
+                            const bool need = SHAPE == STENCIL_BOX || mid || (j >= R && j < R + W);
+                            row[j] = need ? rb[wi * LDX + j] : TC(0);
+                        }
+#pragma unroll
+                        for (int c = -R; c <= R; ++c) {
+                            const int q = ((u - c + R) % Q + Q) % Q;
+#pragma unroll
+                            for (int i = 0; i < WY; ++i) {
+                                const int ao = wi - i - R;
+                                if (ao < -R || ao > R) continue;
+                                if constexpr (SHAPE == STENCIL_BOX) {
+#pragma unroll
+                                    for (int bo = -R; bo <= R; ++bo) {
+                                        const TC wv = weight(((c + R) * (2 * R + 1) + (ao + R)) * (2 * R + 1) + (bo + R));
+#pragma unroll
+                                        for (int j = 0; j < W; ++j)
+                                            acc[s - 1][q][i][j] = fma_c(wv, row[j + bo + R], acc[s - 1][q][i][j]);
+                                    }
+                                } else {
+                                    if (c != 0) {
+                                        if (ao != 0) continue;  // z arm: centre column only
+                                        const TC wv = weight(star3_index<R>(0, c));
+#pragma unroll
+                                        for (int j = 0; j < W; ++j)
+                                            acc[s - 1][q][i][j] = fma_c(wv, row[j + R], acc[s - 1][q][i][j]);
+                                    } else if (ao != 0) {  // y arm
+                                        const TC wv = weight(star3_index<R>(1, ao));
+#pragma unroll
+                                        for (int j = 0; j < W; ++j)
+                                            acc[s - 1][q][i][j] = fma_c(wv, row[j + R], acc[s - 1][q][i][j]);
+                                    } else {  // x arm with the centre
+#pragma unroll
+                                        for (int bo = -R; bo <= R; ++bo) {
+                                            const TC wv = bo == 0 ? weight(0) : weight(star3_index<R>(2, bo));
+#pragma unroll
+                                            for (int j = 0; j < W; ++j)
+                                                acc[s - 1][q][i][j] = fma_c(wv, row[j + bo + R], acc[s - 1][q][i][j]);
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    const int zo = zbase + k - s * (1 + R);
+                    if (s < T) {
+                        TC *wr = &lds[s][par][lpos];
+                        const bool zin = zo >= 0 && zo < n0;
+#pragma unroll
+                        for (int i = 0; i < WY; ++i)
+#pragma unroll
+                            for (int j = 0; j < W; ++j) {
+                                TC v = acc[s - 1][qc][i][j];
+                                if (!periodic && !(zin && row_in[i] && col_in[j])) v = h;
+                                wr[i * LDX + j] = v;
+                            }
+                    } else if (zo >= z0 && zo < z1) {
+                        TS *pl = dst + (int64_t)zo * n1 * n2;
+#pragma unroll
+                        for (int i = 0; i < WY; ++i) {
+                            if (!row_store[i]) continue;
+                            TS *rowp = pl + (int64_t)(cy0 + i) * n2;
+                            Vec ov;
+                            bool all = vec_ok;
+#pragma unroll
+                            for (int j = 0; j < W; ++j) {
+                                ov.e[j] = to_storage<TS>(acc[s - 1][qc][i][j]);
+                                all = all && col_store[j];
+                            }
+                            if (all) {
+                                ov.store(rowp + cx0);
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < W; ++j)
+                                    if (col_store[j]) rowp[cx0 + j] = ov.e[j];
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < WY; ++i)
+#pragma unroll
+                    for (int j = 0; j < W; ++j) acc[s - 1][qc][i][j] = TC(0);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+hipError_t launch_valu3d_cfg(const PassArgs &p, hipStream_t stream)
+{
+    using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    Valu3DArgs<TC, Cfg::K> a;
+    a.src = p.src;
+    a.dst = p.dst;
+    a.n0 = (int)p.dims[0];
+    a.n1 = (int)p.dims[1];
+    a.n2 = (int)p.dims[2];
+    a.oz0 = p.region_lo[0];
+    a.oz1 = p.region_hi[0];
+    a.oy0 = p.region_lo[1];
+    a.oy1 = p.region_hi[1];
+    a.ox0 = p.region_lo[2];
+    a.ox1 = p.region_hi[2];
+    a.periodic = p.boundary == STENCIL_PERIODIC;
+    a.h = (TC)p.halo;
+    for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
+    a.BYv = Cfg::PY - 2 * Cfg::EY;
+    a.BXv = Cfg::PX - 2 * Cfg::EX;
+    if (a.BYv <= 0 || a.BXv <= 0) return hipErrorInvalidValue;
+    const int D0 = a.oz1 - a.oz0, D1 = a.oy1 - a.oy0, D2 = a.ox1 - a.ox0;
+    if (D0 <= 0 || D1 <= 0 || D2 <= 0) return hipSuccess;
+    a.nty = (D1 + a.BYv - 1) / a.BYv;
+    a.ntx = (D2 + a.BXv - 1) / a.BXv;
+    int BZ = p.tile_rows;
+    if (BZ <= 0) {
+        const int target = 8 * (p.num_cu > 0 ? p.num_cu : 256);
+        const int inplane = a.nty * a.ntx;
+        const int segs = (target + inplane - 1) / inplane;
+        BZ = (D0 + segs - 1) / segs;
+        const int minBZ = 8 * R * T > 32 ? 8 * R * T : 32;
+        if (BZ < minBZ) BZ = minBZ;
+    }
+    a.BZ = BZ;
+    a.nzs = (D0 + BZ - 1) / BZ;
+    const int64_t nt = (int64_t)a.nzs * a.nty * a.ntx;
+    if (nt > (1LL << 30)) return hipErrorInvalidValue;
+    a.ntiles = (int)nt;
+    hipLaunchKernelGGL((valu3d_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>), dim3(a.ntiles),
+                       dim3(TX * TY), 0, stream, a);
+    return hipGetLastError();
+}
+
+// Tile shapes: 16 x 16 threads; float64 2x2 points per thread (32 x 32 tile),
+// float32 2 x 4 (32 x 64), 16-bit storage 2 x 8 (32 x 128).
+template <typename TS, typename TC, int SHAPE, int R, int T>
+hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
+{
+    constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
+    constexpr int WY = (R * T >= 6) ? 4 : 2;
+    return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, 16>(p, stream);
+}
+
+#define V3(TS, TC, DT, SH, R, T) \
+    {STENCIL_PATH_VALU, DT, SH, 3, R, T, &launch_valu3d<TS, TC, SH, R, T>}
+#define V3_T(TS, TC, DT, SH, R) V3(TS, TC, DT, SH, R, 1), V3(TS, TC, DT, SH, R, 2), V3(TS, TC, DT, SH, R, 3)
+// Instantiated (shape, r, T): those that fit the register file without
+// spilling; other combinations run as single-step passes of the direct kernel.
+#define V3_S(TS, TC, DT)                                                                      \
+    V3_T(TS, TC, DT, STENCIL_STAR, 1), V3_T(TS, TC, DT, STENCIL_STAR, 2),                     \
+        V3(TS, TC, DT, STENCIL_STAR, 3, 1), V3(TS, TC, DT, STENCIL_STAR, 3, 2),               \
+        V3_T(TS, TC, DT, STENCIL_BOX, 1), V3(TS, TC, DT, STENCIL_BOX, 2, 1)
+
+}  // namespace
+
+const std::vector<KernelEntry> &valu3d_kernels()
+{
+    static const std::vector<KernelEntry> table = {
+        V3_S(double, double, STENCIL_F64),
+        V3_S(float, float, STENCIL_F32),
+    };
+    return table;
+}
+
+}  // namespace stl

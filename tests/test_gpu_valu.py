@@ -109,3 +109,35 @@ def test_in_not_modified_and_alias_rejected(stl):
     with pytest.raises(stl.StencilError) as e:
         p.run(x, x, 3)
     assert e.value.status == "ALIAS"
+
+
+CASES3 = [(shape, r, T, dt) for shape in ("star", "box") for r in (1, 2, 3) for T in (1, 2, 3)
+          for dt in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("shape,r,T,dt", CASES3)
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+def test_valu3d(stl, shape, r, T, dt, boundary):
+    """3D sweeps over several in-plane tiles with ragged edges; combinations
+    without a fused kernel run as single-step passes (same result)."""
+    if shape == "box" and r == 3 and T > 1:
+        pytest.skip("covered by T = 1 (same single-step passes)")
+    dims = (19, 41, 75) if r < 3 else (13, 29, 40)
+    u0, u0r, t, w = case_inputs(shape, 3, r, dims, dt, seed=5000 + 10 * r + T)
+    steps = T + 1
+    p = stl.Plan(shape, 3, r, w, dims, T=T, dtype=dt, path="valu", boundary=boundary, halo=0.5)
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 3, r, w, u0, steps, boundary, 0.5)
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
+def test_config3_shapes_reduced(stl):
+    """Star-3D2R and Box-3D1R, periodic, T = 3 with a remainder pass (50 steps
+    at full size; 8 steps here on 64^3)."""
+    for shape, r in (("star", 2), ("box", 1)):
+        dims = (64, 64, 64)
+        u0, u0r, t, w = case_inputs(shape, 3, r, dims, "f64", seed=5500 + r)
+        p = stl.Plan(shape, 3, r, w, dims, T=3, dtype="f64", path="valu", boundary="periodic")
+        got = run_gpu(p, t, 8)
+        ref = oracle(shape, 3, r, w, u0, 8, "periodic")
+        assert rel_inf(got, ref) <= 1e-12
