@@ -58,12 +58,21 @@ struct KernelEntry {
     hipError_t (*launch)(const PassArgs &, hipStream_t);
 };
 
-// Kernel registries, one per source file.
-const std::vector<KernelEntry> &valu2d_kernels();
+// Kernel registries, one per source file; all_kernel_tables() lists them.
+const std::vector<KernelEntry> &valu2d_table_f64();
+const std::vector<KernelEntry> &valu2d_table_f32();
+const std::vector<KernelEntry> &valu2d_table_bf16();
+const std::vector<KernelEntry> &valu2d_table_f16();
+const std::vector<KernelEntry> &valu2d_table_x3();  // float storage, FP64 arithmetic
 const std::vector<KernelEntry> &valu3d_kernels();
 const std::vector<KernelEntry> &generic_kernels();
-const std::vector<KernelEntry> &mfma2d_kernels();
+const std::vector<KernelEntry> &mfma2d_table_f64();
+const std::vector<KernelEntry> &mfma2d_table_f32();
+const std::vector<KernelEntry> &mfma2d_table_bf16();
+const std::vector<KernelEntry> &mfma2d_table_f16();
+const std::vector<KernelEntry> &mfma2d_table_x3();
 const std::vector<KernelEntry> &mfma3d_kernels();
+std::vector<const std::vector<KernelEntry> *> all_kernel_tables();
 
 const KernelEntry *find_kernel(int path, int dtype, int shape, int d, int r, int t);
 

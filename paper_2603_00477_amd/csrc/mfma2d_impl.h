@@ -1,0 +1,305 @@
+// MFMA path, d = 2: the T-step composite kernel applied once per pass as
+// banded Toeplitz products on the matrix cores (kernel fusion; paper, Sec.
+// "Tensor Core Implementation with Kernel Fusion": executed work (alpha/S)
+// t C, memory traffic unchanged).
+//
+// Workgroup: NW waves side by side; wave w owns V stacked 16 x 16 output
+// tiles (16V rows x 16 columns).  The input block the workgroup needs
+// ((16V + 2R) x (16 NW + 2R) points, halo included, boundary rule applied) is
+// staged once in LDS in the operand type.  For every kernel column b the wave
+// loads that column's A fragments (lane-ordered on the host, L2-resident) and
+// issues one MFMA per (tile, structurally non-zero k-block).  With KDIM = 4
+// (f64/f32) a B fragment of rows 4q..4q+3 serves every stacked tile whose
+// k-block lands on it.  With KDIM = 32 (bf16/f16) the LDS block is stored
+// column-major so each lane's 8 consecutive rows are one 16-byte read.
+//
+// Compensated mode (float32 storage): data split x = x_hi + x_lo and weights
+// w = w_hi + w_lo into bf16; three products hi*hi + hi*lo + lo*hi per term,
+// accumulated in float32.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "mfma_layout.h"
+#include "valu_common.h"
+
+namespace stl {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+template <int DT>
+struct MfmaTypes;
+template <>
+struct MfmaTypes<STENCIL_F64> {
+    using TS = double;   // storage
+    using OP = double;   // operand element
+    using FR = double;   // operand fragment (per lane)
+    using ACC = v4d;
+    static constexpr int KDIM = 4;
+    static constexpr bool X3 = false;
+};
+template <>
+struct MfmaTypes<STENCIL_F32> {
+    using TS = float;
+    using OP = float;
+    using FR = float;
+    using ACC = v4f;
+    static constexpr int KDIM = 4;
+    static constexpr bool X3 = false;
+};
+template <>
+struct MfmaTypes<STENCIL_BF16> {
+    using TS = __hip_bfloat16;
+    using OP = __bf16;
+    using FR = v8bf;
+    using ACC = v4f;
+    static constexpr int KDIM = 32;
+    static constexpr bool X3 = false;
+};
+template <>
+struct MfmaTypes<STENCIL_F16> {
+    using TS = __half;
+    using OP = _Float16;
+    using FR = v8h;
+    using ACC = v4f;
+    static constexpr int KDIM = 32;
+    static constexpr bool X3 = false;
+};
+template <>
+struct MfmaTypes<STENCIL_F32_BF16X3> {
+    using TS = float;
+    using OP = __bf16;
+    using FR = v8bf;
+    using ACC = v4f;
+    static constexpr int KDIM = 32;
+    static constexpr bool X3 = true;
+};
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(v8bf a, v8bf b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(v8h a, v8h b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// storage value -> compute float/double
+template <typename TS>
+__device__ __forceinline__ auto load_val(TS v)
+{
+    if constexpr (sizeof(TS) == 2) return to_compute<float>(v);
+    else return v;
+}
+
+template <typename OP, typename X>
+__device__ __forceinline__ OP to_op(X v)
+{
+    if constexpr (sizeof(OP) == 2) return (OP)(float)v;  // round to nearest even
+    else return (OP)v;
+}
+
+struct Mfma2DArgs {
+    const void *src;
+    void *dst;
+    const void *afrag;
+    const void *afrag_lo;
+    int n0, n1;
+    int ntr, ntc, ntiles;
+    int periodic;
+    double h;
+};
+
+template <int DT, int SHAPE, int r, int T, int V, int NW>
+struct Mfma2DCfg {
+    using MT = MfmaTypes<DT>;
+    static constexpr int KDIM = MT::KDIM;
+    static constexpr int KPL = KDIM / 4;
+    static constexpr int R = r * T;
+    static constexpr int TR = 16 * V;          // output rows per workgroup
+    static constexpr int TCOL = 16 * NW;       // output columns per workgroup
+    static constexpr int LRD = TR + 2 * R;     // data rows staged
+    static constexpr int LC = TCOL + 2 * R;    // data columns staged
+    static constexpr int KKH = band_kk_hi(SHAPE, r, T, 0, 0, KDIM);
+    static constexpr int LRK = 16 * (V - 1) + KDIM * (KKH + 1);  // rows an operand may touch
+    static constexpr int LR0 = LRD > LRK ? LRD : LRK;
+    static constexpr int LR = ((LR0 + 7) / 8) * 8;
+    // row-major pitch (KDIM = 4) padded off multiples of the bank count
+    static constexpr int LCP = LC + ((LC % 32) == 0 ? 1 : 0);
+    static constexpr int LDS_ELEMS = KDIM == 4 ? LR * LCP : LC * LR;
+};
+
+template <int DT, int SHAPE, int r, int T, int V, int NW>
+__global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
+{
+    using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
+    using MT = typename Cfg::MT;
+    using TS = typename MT::TS;
+    using OP = typename MT::OP;
+    using FR = typename MT::FR;
+    using ACC = typename MT::ACC;
+    constexpr int KDIM = Cfg::KDIM, R = Cfg::R;
+    constexpr int LR = Cfg::LR, LRD = Cfg::LRD, LC = Cfg::LC, LCP = Cfg::LCP;
+    constexpr int NT = 64 * NW;
+    constexpr bool X3 = MT::X3;
+
+    __shared__ __attribute__((aligned(16))) OP lhi[Cfg::LDS_ELEMS];
+    __shared__ __attribute__((aligned(16))) OP llo[X3 ? Cfg::LDS_ELEMS : 1];
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    const int tr = tile / a.ntc, tcn = tile - tr * a.ntc;
+    const int r0 = tr * Cfg::TR, c0 = tcn * Cfg::TCOL;
+    const int n0 = a.n0, n1 = a.n1;
+    const bool periodic = a.periodic != 0;
+    const TS *src = static_cast<const TS *>(a.src);
+
+    // ---- stage the input block (boundary rule applied) in LDS
+    for (int idx = tid; idx < LR * LC; idx += NT) {
+        const int row = idx / LC, col = idx - (idx / LC) * LC;
+        float vf = 0.f;
+        double vd = 0.0;
+        if (row < LRD) {
+            int gr = r0 - R + row, gc = c0 - R + col;
+            const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
+            if (in || periodic) {
+                gr = wrap(gr, n0);
+                gc = wrap(gc, n1);
+                const auto v = load_val(src[(int64_t)gr * n1 + gc]);
+                vf = (float)v;
+                vd = (double)v;
+            } else {
+                vf = (float)a.h;
+                vd = a.h;
+            }
+        }
+        const int li = KDIM == 4 ? row * LCP + col : col * LR + row;
+        if constexpr (sizeof(OP) == 8) {
+            lhi[li] = vd;
+        } else if constexpr (sizeof(OP) == 4) {
+            lhi[li] = vf;
+        } else if constexpr (X3) {
+            const OP hi = (OP)vf;
+            lhi[li] = hi;
+            llo[li] = (OP)(vf - (float)hi);
+        } else {
+            lhi[li] = (OP)vf;
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lg = lane >> 4, ln = lane & 15;
+    const int wc0 = 16 * wave;
+    ACC acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = ACC{};
+
+    const FR *afr = static_cast<const FR *>(a.afrag);
+    const FR *afr_lo = static_cast<const FR *>(a.afrag_lo);
+
+#pragma unroll
+    for (int b = -R; b <= R; ++b) {
+        const int amax = band_amax(SHAPE, r, T, 0, b);
+        if (amax < 0) continue;
+        const int klo = band_kk_lo(SHAPE, r, T, 0, b, KDIM);
+        const int khi = band_kk_hi(SHAPE, r, T, 0, b, KDIM);
+        const int off = band_frag_offset(SHAPE, r, T, 0, b, KDIM, 2);
+        constexpr int NBMAX = band_nblk(SHAPE, r, T, 0, 0, KDIM);
+        FR A[NBMAX], Alo[X3 ? NBMAX : 1];
+#pragma unroll
+        for (int i = 0; i < NBMAX; ++i)
+            if (i <= khi - klo) {
+                A[i] = afr[(off + i) * 64 + lane];
+                if constexpr (X3) Alo[i] = afr_lo[(off + i) * 64 + lane];
+            }
+        const int col = wc0 + ln + b + R;
+        if constexpr (KDIM == 4) {
+#pragma unroll
+            for (int q = 0; q < NBMAX + 4 * (V - 1) + 4; ++q) {
+                const int qq = klo + q;
+                if (qq > khi + 4 * (V - 1)) break;
+                const FR B = lhi[(4 * qq + lg) * LCP + col];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int kk = qq - 4 * v;
+                    if (kk >= klo && kk <= khi) acc[v] = mfma16(A[kk - klo], B, acc[v]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int i = 0; i < NBMAX; ++i) {
+                    if (i > khi - klo) break;
+                    const int row = 16 * v + KDIM * (klo + i) + 8 * lg;
+                    const FR B = *reinterpret_cast<const FR *>(&lhi[col * LR + row]);
+                    acc[v] = mfma16(A[i], B, acc[v]);
+                    if constexpr (X3) {
+                        const FR Bl = *reinterpret_cast<const FR *>(&llo[col * LR + row]);
+                        acc[v] = mfma16(A[i], Bl, acc[v]);
+                        acc[v] = mfma16(Alo[i], B, acc[v]);
+                    }
+                }
+        }
+    }
+
+    // ---- store: lane holds D[4*lg + e][ln] of each stacked tile
+    TS *dst = static_cast<TS *>(a.dst);
+    const int gc = c0 + wc0 + ln;
+    if (gc < n1) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gr = r0 + 16 * v + 4 * lg + e;
+                if (gr < n0) dst[(int64_t)gr * n1 + gc] = to_storage<TS>(acc[v][e]);
+            }
+    }
+}
+
+template <int DT, int SHAPE, int r, int T>
+hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
+{
+    constexpr int V = 4, NW = 4;
+    using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
+    if (p.steps != T || !p.afrag) return hipErrorInvalidValue;
+    if (MfmaTypes<DT>::X3 && !p.afrag_lo) return hipErrorInvalidValue;
+    Mfma2DArgs a;
+    a.src = p.src;
+    a.dst = p.dst;
+    a.afrag = p.afrag;
+    a.afrag_lo = p.afrag_lo;
+    a.n0 = (int)p.dims[0];
+    a.n1 = (int)p.dims[1];
+    a.periodic = p.boundary == STENCIL_PERIODIC;
+    a.h = p.halo;
+    a.ntr = (a.n0 + Cfg::TR - 1) / Cfg::TR;
+    a.ntc = (a.n1 + Cfg::TCOL - 1) / Cfg::TCOL;
+    a.ntiles = a.ntr * a.ntc;
+    hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW>), dim3(a.ntiles), dim3(64 * NW), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+#define M2(DT, SH, R, T) {STENCIL_PATH_MFMA, DT, SH, 2, R, T, &launch_mfma2d<DT, SH, R, T>}
+#define M2_T(DT, SH, R) M2(DT, SH, R, 1), M2(DT, SH, R, 2), M2(DT, SH, R, 3), M2(DT, SH, R, 4)
+#define M2_R(DT, SH) M2_T(DT, SH, 1), M2_T(DT, SH, 2), M2_T(DT, SH, 3)
+#define M2_S(DT) M2_R(DT, STENCIL_STAR), M2_R(DT, STENCIL_BOX)
+
+}  // namespace stl

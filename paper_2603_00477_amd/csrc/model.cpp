@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "mfma_layout.h"
 
 namespace stl {
 
@@ -77,22 +78,12 @@ MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype)
     L.Kp = ceil_div(16 + 2 * L.R, L.kdim) * L.kdim;
     L.nblk = L.Kp / L.kdim;
     const double KT = (double)fused_points(shape, d, r, steps);
-    double executed;  // MACs per output point
-    if (d == 2) {
-        if (shape == STENCIL_STAR && steps == 1)
-            executed = 2.0 * L.Kp;  // vertical arm as a column band, horizontal arm as a row band
-        else
-            executed = (2.0 * L.R + 1) * L.Kp;  // one column band per kernel column
-    } else {
-        // one band per (plane, column) pair that holds a non-zero
-        const double cols = shape == STENCIL_BOX ? (2.0 * L.R + 1) * (2.0 * L.R + 1)
-                                                 : (double)fused_points(STENCIL_STAR, 2, r, steps);
-        executed = cols * L.Kp;
-    }
+    // MACs issued per output point: KDIM per structurally non-zero k-block of
+    // every column band (see mfma_layout.h)
+    const double executed = (double)band_total_frags(shape, r, steps, L.kdim, d) * L.kdim;
     L.S = KT / executed;
     return L;
 }
-
 
 }  // namespace stl
 

@@ -131,9 +131,7 @@ int device_cu_count()
 
 const KernelEntry *find_kernel(int path, int dtype, int shape, int d, int r, int t)
 {
-    const std::vector<KernelEntry> *tables[] = {&valu2d_kernels(), &valu3d_kernels(),
-                                                &mfma2d_kernels(), &mfma3d_kernels(),
-                                                &generic_kernels()};
+    static const std::vector<const std::vector<KernelEntry> *> tables = all_kernel_tables();
     for (const auto *tab : tables)
         for (const auto &e : *tab)
             if (e.path == path && e.dtype == dtype && e.d == d && (e.shape == shape || e.shape < 0) &&

@@ -26,6 +26,8 @@
 // The kernel writes an arbitrary output rectangle [oy0,oy1) x [ox0,ox1), used
 // both for whole grids and for the Dirichlet boundary band of the MFMA path.
 
+#pragma once
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -34,7 +36,6 @@
 #include "valu_common.h"
 
 namespace stl {
-namespace {
 
 template <typename TC, int K>
 struct Valu2DArgs {
@@ -303,16 +304,5 @@ hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
     V2(TS, TC, DT, SH, R, 1), V2(TS, TC, DT, SH, R, 2), V2(TS, TC, DT, SH, R, 3), V2(TS, TC, DT, SH, R, 4)
 #define V2_R(TS, TC, DT, SH) V2_T(TS, TC, DT, SH, 1), V2_T(TS, TC, DT, SH, 2), V2_T(TS, TC, DT, SH, 3)
 #define V2_S(TS, TC, DT) V2_R(TS, TC, DT, STENCIL_STAR), V2_R(TS, TC, DT, STENCIL_BOX)
-
-}  // namespace
-
-const std::vector<KernelEntry> &valu2d_kernels()
-{
-    static const std::vector<KernelEntry> table = {
-        V2_S(double, double, STENCIL_F64),
-        V2_S(float, float, STENCIL_F32),
-    };
-    return table;
-}
 
 }  // namespace stl

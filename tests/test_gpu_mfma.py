@@ -1,0 +1,95 @@
+"""GPU parity of the MFMA path (kernel fusion as banded Toeplitz products)
+against the FP64 oracle.
+
+FP64 <= 1e-12 and FP32 <= 1e-5 relative max-norm error.  16-bit modes are
+checked for arithmetic error (oracle run on the storage-rounded input, with
+the float64 weights) against a per-pass bound
+    passes * (2 u_store + u_w + K_T * 2^-24)
+where u_store is the storage unit roundoff, u_w the rounding of the
+composite weights (bf16 2^-9, f16 2^-11, compensated hi/lo split 2^-17) and
+K_T * 2^-24 bounds float32 accumulation of K_T terms of a non-expansive
+operator (weights >= 0, sum 1)."""
+import numpy as np
+import pytest
+
+from gpu_util import case_inputs, oracle, rel_inf, run_gpu
+from oracle import model as omodel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+U_STORE = {"bf16": 2.0 ** -9, "f16": 2.0 ** -11, "bf16x3": 2.0 ** -24}
+U_W = {"bf16": 2.0 ** -9, "f16": 2.0 ** -11, "bf16x3": 2.0 ** -17}
+
+
+@pytest.fixture(scope="module")
+def stl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_00477_amd as stl
+    stl.lib()
+    return stl
+
+
+CASES = [(shape, r, T, dt) for shape in ("star", "box") for r in (1, 2, 3) for T in (1, 2, 3, 4)
+         for dt in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("shape,r,T,dt", CASES)
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+def test_mfma2d(stl, shape, r, T, dt, boundary):
+    dims = (150, 217)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6000 + 10 * r + T)
+    steps = 2 * T + (1 if T > 1 else 0)
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma", boundary=boundary, halo=0.125)
+    assert p.info()["path_name"] == "mfma"
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0, steps, boundary, 0.125)
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
+def test_mfma_matches_valu_f64(stl):
+    dims = (257, 300)
+    u0, u0r, t, w = case_inputs("box", 2, 3, dims, "f64", seed=6100)
+    outs = {}
+    for path in ("valu", "mfma"):
+        p = stl.Plan("box", 2, 3, w, dims, T=2, dtype="f64", path=path)
+        outs[path] = run_gpu(p, t, 6)
+    assert rel_inf(outs["mfma"], outs["valu"]) <= 1e-13
+
+
+def _bound(dt, shape, d, r, T, steps):
+    KT = omodel.K_fused(shape, d, r, T)
+    passes = -(-steps // T)
+    return passes * (2 * U_STORE[dt] + U_W[dt] + KT * 2.0 ** -24)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "bf16x3"])
+@pytest.mark.parametrize("shape,r,T", [("box", 2, 1), ("box", 2, 2), ("box", 2, 4), ("star", 1, 3),
+                                       ("box", 3, 2), ("star", 3, 1)])
+@pytest.mark.parametrize("boundary", ["periodic", "dirichlet"])
+def test_mfma2d_low_precision(stl, dt, shape, r, T, boundary):
+    dims = (160, 300)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6200 + 10 * r + T)
+    steps = 2 * T
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma", boundary=boundary)
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0r, steps, boundary)
+    err = rel_inf(got, ref)
+    assert err <= _bound(dt, shape, 2, r, T, steps), err
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("T", [1, 2, 4])
+def test_valu2d_low_precision_storage(stl, dt, T):
+    """VALU path on 16-bit storage with float32 arithmetic (intermediate steps
+    of a pass kept in float32 on chip)."""
+    dims = (130, 2100)
+    u0, u0r, t, w = case_inputs("box", 2, 2, dims, dt, seed=6300 + T)
+    steps = 2 * T + 1
+    p = stl.Plan("box", 2, 2, w, dims, T=T, dtype=dt, path="valu", boundary="periodic")
+    got = run_gpu(p, t, steps)
+    ref = oracle("box", 2, 2, w, u0r, steps, "periodic")
+    passes = -(-steps // T)
+    assert rel_inf(got, ref) <= passes * (U_STORE[dt] + 25 * T * 2.0 ** -24)
