@@ -99,14 +99,14 @@ hipError_t launch_generic(const PassArgs &p, hipStream_t stream)
 const std::vector<KernelEntry> &generic_kernels()
 {
     static const std::vector<KernelEntry> table = {
-        {STENCIL_PATH_VALU, STENCIL_F64, -1, 2, -1, 1, &launch_generic<double, double>},
-        {STENCIL_PATH_VALU, STENCIL_F64, -1, 3, -1, 1, &launch_generic<double, double>},
-        {STENCIL_PATH_VALU, STENCIL_F32, -1, 2, -1, 1, &launch_generic<float, float>},
-        {STENCIL_PATH_VALU, STENCIL_F32, -1, 3, -1, 1, &launch_generic<float, float>},
-        {STENCIL_PATH_VALU, STENCIL_BF16, -1, 2, -1, 1, &launch_generic<__hip_bfloat16, float>},
-        {STENCIL_PATH_VALU, STENCIL_BF16, -1, 3, -1, 1, &launch_generic<__hip_bfloat16, float>},
-        {STENCIL_PATH_VALU, STENCIL_F16, -1, 2, -1, 1, &launch_generic<__half, float>},
-        {STENCIL_PATH_VALU, STENCIL_F16, -1, 3, -1, 1, &launch_generic<__half, float>},
+        {STENCIL_PATH_VALU, STENCIL_F64, -1, 2, -1, 1, &launch_generic<double, double>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_F64, -1, 3, -1, 1, &launch_generic<double, double>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_F32, -1, 2, -1, 1, &launch_generic<float, float>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_F32, -1, 3, -1, 1, &launch_generic<float, float>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_BF16, -1, 2, -1, 1, &launch_generic<__hip_bfloat16, float>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_BF16, -1, 3, -1, 1, &launch_generic<__hip_bfloat16, float>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_F16, -1, 2, -1, 1, &launch_generic<__half, float>, nullptr},
+        {STENCIL_PATH_VALU, STENCIL_F16, -1, 3, -1, 1, &launch_generic<__half, float>, nullptr},
     };
     return table;
 }

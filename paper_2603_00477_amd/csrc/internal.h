@@ -47,6 +47,26 @@ struct PassArgs {
     int num_cu;
 };
 
+// Device copies of small host tables (job lists of batched launches).  put()
+// copies `bytes` into a pinned host region and enqueues its upload on
+// `stream`; regions handed out since begin() stay valid until the next
+// begin(), which first waits for the previous call's uploads to finish.
+class BatchStaging {
+public:
+    hipError_t begin(hipStream_t stream);
+    hipError_t put(const void *host, size_t bytes, void **dev, hipStream_t stream);
+    hipError_t end(hipStream_t stream);
+    ~BatchStaging();
+
+private:
+    hipError_t grow(size_t need, hipStream_t stream);
+    uint8_t *host_ = nullptr;
+    uint8_t *dev_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
+    hipEvent_t done_ = nullptr;
+    bool pending_ = false;
+};
+
 // One launchable kernel variant.
 struct KernelEntry {
     int path;    // STENCIL_PATH_VALU or STENCIL_PATH_MFMA
@@ -56,6 +76,8 @@ struct KernelEntry {
     int r;       // -1 = any
     int t;       // steps per pass, -1 = any
     hipError_t (*launch)(const PassArgs &, hipStream_t);
+    // n passes of this variant (different grids) in one persistent launch; may be null
+    hipError_t (*launch_batch)(const PassArgs *, int, BatchStaging *, hipStream_t) = nullptr;
 };
 
 // Kernel registries, one per source file; all_kernel_tables() lists them.

@@ -43,6 +43,8 @@ struct MfmaTypes<STENCIL_F64> {
     using ACC = v4d;
     static constexpr int KDIM = 4;
     static constexpr bool X3 = false;
+    // f64 16x16x4: register e of lane l holds D[4e + l/16][l % 16]
+    static constexpr bool D_ROW_INTERLEAVED = true;
 };
 template <>
 struct MfmaTypes<STENCIL_F32> {
@@ -52,6 +54,8 @@ struct MfmaTypes<STENCIL_F32> {
     using ACC = v4f;
     static constexpr int KDIM = 4;
     static constexpr bool X3 = false;
+    // register e of lane l holds D[4 (l/16) + e][l % 16]
+    static constexpr bool D_ROW_INTERLEAVED = false;
 };
 template <>
 struct MfmaTypes<STENCIL_BF16> {
@@ -61,6 +65,8 @@ struct MfmaTypes<STENCIL_BF16> {
     using ACC = v4f;
     static constexpr int KDIM = 32;
     static constexpr bool X3 = false;
+    // register e of lane l holds D[4 (l/16) + e][l % 16]
+    static constexpr bool D_ROW_INTERLEAVED = false;
 };
 template <>
 struct MfmaTypes<STENCIL_F16> {
@@ -70,6 +76,8 @@ struct MfmaTypes<STENCIL_F16> {
     using ACC = v4f;
     static constexpr int KDIM = 32;
     static constexpr bool X3 = false;
+    // register e of lane l holds D[4 (l/16) + e][l % 16]
+    static constexpr bool D_ROW_INTERLEAVED = false;
 };
 template <>
 struct MfmaTypes<STENCIL_F32_BF16X3> {
@@ -79,6 +87,8 @@ struct MfmaTypes<STENCIL_F32_BF16X3> {
     using ACC = v4f;
     static constexpr int KDIM = 32;
     static constexpr bool X3 = true;
+    // register e of lane l holds D[4 (l/16) + e][l % 16]
+    static constexpr bool D_ROW_INTERLEAVED = false;
 };
 
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c)
@@ -259,7 +269,7 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
         }
     }
 
-    // ---- store: lane holds D[4*lg + e][ln] of each stacked tile
+    // ---- store the stacked tiles (output register layout per instruction)
     TS *dst = static_cast<TS *>(a.dst);
     const int gc = c0 + wc0 + ln;
     if (gc < n1) {
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
         for (int v = 0; v < V; ++v)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gr = r0 + 16 * v + 4 * lg + e;
+                const int gr = r0 + 16 * v + (MT::D_ROW_INTERLEAVED ? 4 * e + lg : 4 * lg + e);
                 if (gr < n0) dst[(int64_t)gr * n1 + gc] = to_storage<TS>(acc[v][e]);
             }
     }
@@ -297,7 +307,7 @@ hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
     return hipGetLastError();
 }
 
-#define M2(DT, SH, R, T) {STENCIL_PATH_MFMA, DT, SH, 2, R, T, &launch_mfma2d<DT, SH, R, T>}
+#define M2(DT, SH, R, T) {STENCIL_PATH_MFMA, DT, SH, 2, R, T, &launch_mfma2d<DT, SH, R, T>, nullptr}
 #define M2_T(DT, SH, R) M2(DT, SH, R, 1), M2(DT, SH, R, 2), M2(DT, SH, R, 3), M2(DT, SH, R, 4)
 #define M2_R(DT, SH) M2_T(DT, SH, 1), M2_T(DT, SH, 2), M2_T(DT, SH, 3)
 #define M2_S(DT) M2_R(DT, STENCIL_STAR), M2_R(DT, STENCIL_BOX)

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -183,8 +184,12 @@ int resolve_path(stencil_plan_s *p)
     const bool v = has_path(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T);
     const bool m = has_path(STENCIL_PATH_MFMA, p->dtype, p->shape, p->d, p->r, p->T);
     int path = p->path_req;
-    if (path == STENCIL_PATH_AUTO) path = (p->pred_winner > 0 && m) ? STENCIL_PATH_MFMA
-                                                                    : (v ? STENCIL_PATH_VALU : STENCIL_PATH_MFMA);
+    if (path == STENCIL_PATH_AUTO) {
+        // the compensated mode exists only on the matrix path (its VALU
+        // instances serve the Dirichlet band fix-up)
+        if (p->dtype == STENCIL_F32_BF16X3) path = STENCIL_PATH_MFMA;
+        else path = (p->pred_winner > 0 && m) ? STENCIL_PATH_MFMA : (v ? STENCIL_PATH_VALU : STENCIL_PATH_MFMA);
+    }
     if (path == STENCIL_PATH_VALU && !v)
         return fail(STENCIL_ERR_UNSUPPORTED, "VALU path not built for this dtype/shape/d/r");
     if (path == STENCIL_PATH_MFMA && !m)
@@ -227,19 +232,35 @@ size_t fragment_bytes(const stencil_plan_s *p)
     return total;
 }
 
-int ensure_device(stencil_plan_s *p)
+int upload_fragments(stencil_plan_s *p);
+
+// Device state of a plan on the current device: MFMA operands always, the
+// ping-pong scratch grid only when a run needs two or more passes.
+int ensure_device(stencil_plan_s *p, bool need_scratch)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
-    if (p->device == dev && p->scratch) return STENCIL_OK;
-    free_device(p);
-    e = hipMalloc(&p->scratch, std::max<size_t>(grid_bytes(p), 256));
-    if (e != hipSuccess) {
-        p->scratch = nullptr;
-        return fail(STENCIL_ERR_OOM, std::string("hipMalloc scratch: ") + hipGetErrorString(e));
+    if (p->device != dev) {
+        free_device(p);
+        int rc = upload_fragments(p);
+        if (rc) return rc;
+        p->device = dev;
     }
-    p->scratch_bytes = grid_bytes(p);
+    if (need_scratch && !p->scratch) {
+        e = hipMalloc(&p->scratch, std::max<size_t>(grid_bytes(p), 256));
+        if (e != hipSuccess) {
+            p->scratch = nullptr;
+            return fail(STENCIL_ERR_OOM, std::string("hipMalloc scratch: ") + hipGetErrorString(e));
+        }
+        p->scratch_bytes = grid_bytes(p);
+    }
+    return STENCIL_OK;
+}
+
+int upload_fragments(stencil_plan_s *p)
+{
+    hipError_t e;
     if (p->path == STENCIL_PATH_MFMA) {
         p->afrag.assign(p->T + 1, nullptr);
         p->afrag_lo.assign(p->T + 1, nullptr);
@@ -266,7 +287,6 @@ int ensure_device(stencil_plan_s *p)
             }
         }
     }
-    p->device = dev;
     return STENCIL_OK;
 }
 
@@ -393,18 +413,30 @@ int run_one(stencil_plan_s *p, const void *in, void *out, int64_t steps, hipStre
     return STENCIL_OK;
 }
 
-// Batched runs: round j issues pass j of every job that has one, so passes of
-// different jobs overlap on the device queue while each job's passes stay in
-// order.  Each job ping-pongs exactly as in run_one, so results are identical.
+// Batched runs: round j issues pass j of every job that has one.  Passes of
+// one round that share a kernel variant go out as one persistent batched
+// launch (workgroups pull tiles of all those grids from one list); the rest
+// (MFMA passes, Dirichlet fix-ups) are launched one by one.  Each job's
+// passes stay in stream order and ping-pong exactly as in run_one, so every
+// result is bit-identical to running the job alone.
+std::mutex g_batch_mu;
+
 int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *const *outs,
               const int64_t *steps, hipStream_t stream)
 {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    static std::map<int, BatchStaging> stages;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    BatchStaging &stage = stages[dev];
+    hipError_t e = stage.begin(stream);
+    if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batch staging: ") + hipGetErrorString(e));
+
     std::vector<std::vector<PassDesc>> sched((size_t)n);
     size_t rounds = 0;
     for (int i = 0; i < n; ++i) {
         if (steps[i] == 0) {
-            hipError_t e = hipMemcpyAsync(outs[i], ins[i], grid_bytes(plans[i]),
-                                          hipMemcpyDeviceToDevice, stream);
+            e = hipMemcpyAsync(outs[i], ins[i], grid_bytes(plans[i]), hipMemcpyDeviceToDevice, stream);
             if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
             continue;
         }
@@ -413,6 +445,7 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
     }
     std::vector<const void *> src(ins, ins + n);
     for (size_t j = 0; j < rounds; ++j) {
+        std::map<const KernelEntry *, std::vector<PassArgs>> groups;
         for (int i = 0; i < n; ++i) {
             const auto &ps = sched[i];
             if (j >= ps.size()) continue;
@@ -424,16 +457,29 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
             PassArgs a = base_args(p, pd.t);
             a.src = src[i];
             a.dst = dst;
+            src[i] = dst;
+            if (pd.k->launch_batch && !pd.fixup && pd.path == STENCIL_PATH_VALU) {
+                groups[pd.k].push_back(a);
+                continue;
+            }
             if (pd.path == STENCIL_PATH_MFMA) {
                 a.afrag = p->afrag[pd.t];
                 a.afrag_lo = p->afrag_lo[pd.t];
             }
-            hipError_t e = pd.k->launch(a, stream);
-            if (e == hipSuccess && pd.fixup) e = launch_fixup(p, pd.t, src[i], dst, stream);
+            e = pd.k->launch(a, stream);
+            if (e == hipSuccess && pd.fixup) e = launch_fixup(p, pd.t, a.src, dst, stream);
             if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
-            src[i] = dst;
+        }
+        for (auto &g : groups) {
+            const KernelEntry *k = g.first;
+            auto &v = g.second;
+            e = v.size() == 1 ? k->launch(v[0], stream)
+                              : k->launch_batch(v.data(), (int)v.size(), &stage, stream);
+            if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(e));
         }
     }
+    e = stage.end(stream);
+    if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batch staging: ") + hipGetErrorString(e));
     return STENCIL_OK;
 }
 
@@ -603,7 +649,7 @@ extern "C" int stencil_run(stencil_plan_t p, const void *in, void *out, int64_t 
     if (!p || !in || !out) return fail(STENCIL_ERR_INVALID_ARG, "stencil_run: NULL plan or buffer");
     if (steps < 0) return fail(STENCIL_ERR_INVALID_ARG, "stencil_run: steps < 0");
     if (overlap(in, out, grid_bytes(p))) return fail(STENCIL_ERR_ALIAS, "stencil_run: in and out overlap");
-    int rc = ensure_device(p);
+    int rc = ensure_device(p, steps > 0 && schedule(p, steps).size() > 1);
     if (rc) return rc;
     return run_one(p, in, out, steps, (hipStream_t)stream);
 }
@@ -623,7 +669,7 @@ extern "C" int stencil_run_batch(int n, const stencil_plan_t *plans, const void 
             if (plans[j] == plans[i]) return fail(STENCIL_ERR_INVALID_ARG, "stencil_run_batch: repeated plan");
     }
     for (int i = 0; i < n; ++i) {
-        int rc = ensure_device(plans[i]);
+        int rc = ensure_device(plans[i], schedule(plans[i], steps[i]).size() > 1);
         if (rc) return rc;
     }
     return run_batch(n, plans, ins, outs, steps, (hipStream_t)stream);

@@ -37,8 +37,9 @@
 
 namespace stl {
 
-template <typename TC, int K>
-struct Valu2DArgs {
+// Geometry of one pass of one grid: output box, tiling and boundary.
+template <typename TC>
+struct Valu2DJob {
     const void *src;
     void *dst;
     int n0, n1;
@@ -46,6 +47,11 @@ struct Valu2DArgs {
     int BX, BY, nbands, nsegs, ntiles;
     int periodic;
     TC h;
+};
+
+template <typename TC, int K>
+struct Valu2DArgs {
+    Valu2DJob<TC> g;
     TC w[K];
 };
 
@@ -68,9 +74,13 @@ __device__ __forceinline__ int star_axis_index(int axis, int off)
     return 1 + axis * 2 * R + (off < 0 ? off + R : off + R - 1);
 }
 
+// One tile (column band x row segment) of one pass.  `wk` holds the weights,
+// `lds` the stage row buffers; the caller provides both.
 template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
-__global__ __launch_bounds__(NT) void valu2d_kernel(
-    Valu2DArgs<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K> a)
+__device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
+                                            const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K],
+                                            int tile,
+                                            TC (&lds)[T][2][Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::LROW])
 {
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
     constexpr int Q = Cfg::Q;
@@ -79,12 +89,7 @@ __global__ __launch_bounds__(NT) void valu2d_kernel(
     constexpr int PADL = Cfg::PADL;
     using Vec = RawVec<TS, W>;
 
-    __shared__ TC lds[T][2][LROW];
-
     const int tid = threadIdx.x;
-    // XCD-aware tile order: blocks that land on one XCD take consecutive tiles
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= a.ntiles) return;
     const int band = tile / a.nsegs;
     const int seg = tile - band * a.nsegs;
     const int x0 = a.ox0 + band * a.BX;
@@ -100,7 +105,7 @@ __global__ __launch_bounds__(NT) void valu2d_kernel(
     const bool periodic = a.periodic != 0;
     const TC h = a.h;
 
-    // zero the LDS pads once (never written afterwards)
+    // zero the LDS pads (never written by the pipeline)
     for (int i = tid; i < T * 2 * LROW; i += NT) (&lds[0][0][0])[i] = TC(0);
 
     // per-column facts
@@ -116,16 +121,6 @@ __global__ __launch_bounds__(NT) void valu2d_kernel(
     }
     const bool vec_ok = vec_aligned<TS, W>(src, n1, cb) && cb >= 0 && cb + W <= n1;
     const TS hs = to_storage<TS>(h);
-
-    // Weights: scalar registers hold up to ~48 dwords of them; larger sets
-    // (49 float64 box weights) are pinned in vector registers, otherwise the
-    // compiler spills them to vector lanes and pays a readlane per use.
-    TC wk[Cfg::K];
-#pragma unroll
-    for (int k = 0; k < Cfg::K; ++k) {
-        wk[k] = a.w[k];
-        if constexpr (sizeof(TC) * Cfg::K > 192) asm volatile("" : "+v"(wk[k]));
-    }
 
     const int KTOT = BYe + 2 * R * T + T;
     const int ybase = y0 - R * T;
@@ -257,49 +252,168 @@ __global__ __launch_bounds__(NT) void valu2d_kernel(
     }
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T>
-hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
+// Load the weights.  Scalar registers hold up to ~48 dwords; larger sets
+// (49 float64 box weights) are pinned in vector registers, otherwise the
+// compiler spills them to vector lanes and pays a readlane per use.
+template <typename TC, int K, typename SrcT>
+__device__ __forceinline__ void load_weights(TC (&wk)[K], const SrcT *w)
 {
-    constexpr int W = 16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS);
-    constexpr int NT = 256;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        wk[k] = w[k];
+        if constexpr (sizeof(TC) * K > 192) asm volatile("" : "+v"(wk[k]));
+    }
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
+__global__ __launch_bounds__(NT) void valu2d_kernel(
+    Valu2DArgs<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K> a)
+{
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
-    Valu2DArgs<TC, Cfg::K> a;
-    a.src = p.src;
-    a.dst = p.dst;
-    a.n0 = (int)p.dims[0];
-    a.n1 = (int)p.dims[1];
-    a.oy0 = p.region_lo[0];
-    a.oy1 = p.region_hi[0];
-    a.ox0 = p.region_lo[1];
-    a.ox1 = p.region_hi[1];
-    a.periodic = p.boundary == STENCIL_PERIODIC;
-    a.h = (TC)p.halo;
-    for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
-    a.BX = Cfg::NC - 2 * Cfg::E;
-    if (a.BX <= 0) return hipErrorInvalidValue;
-    const int W_out = a.ox1 - a.ox0, H_out = a.oy1 - a.oy0;
-    if (W_out <= 0 || H_out <= 0) return hipSuccess;
-    a.nbands = (W_out + a.BX - 1) / a.BX;
+    __shared__ TC lds[T][2][Cfg::LROW];
+    // XCD-aware tile order: blocks that land on one XCD take consecutive tiles
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.g.ntiles) return;
+    TC wk[Cfg::K];
+    load_weights(wk, a.w);
+    valu2d_tile<TS, TC, SHAPE, R, T, W, NT>(a.g, wk, tile, lds);
+}
+
+// One job of a batched launch: geometry plus weights.
+template <typename TC, int K>
+struct Valu2DBatchJob {
+    Valu2DJob<TC> g;
+    TC w[K];
+};
+
+// Persistent batched launch: the workgroups walk one list of (job, tile)
+// items spanning every job of the batch (jobs of uneven sizes), item i owned
+// by workgroup i mod gridDim.  tile_start[j] is the first item of job j
+// (tile_start[njobs] = total).
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
+__global__ __launch_bounds__(NT) void valu2d_batch_kernel(
+    const Valu2DBatchJob<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K> *jobs,
+    const int *tile_start, int njobs)
+{
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
+    __shared__ TC lds[T][2][Cfg::LROW];
+    const int total = tile_start[njobs];
+    int j = 0;
+    for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
+        while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
+        const Valu2DJob<TC> g = jobs[j].g;
+        TC wk[Cfg::K];
+        load_weights(wk, jobs[j].w);
+        valu2d_tile<TS, TC, SHAPE, R, T, W, NT>(g, wk, item - tile_start[j], lds);
+        __syncthreads();
+    }
+}
+
+template <typename TS>
+struct Valu2DShape {
+    static constexpr int W = 16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS);
+    static constexpr int NT = 256;
+};
+
+// Fill the geometry of one pass; returns false when there is nothing to do.
+template <typename TS, typename TC, int SHAPE, int R, int T>
+bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
+{
+    using S = Valu2DShape<TS>;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W, S::NT>;
+    *err = hipSuccess;
+    g->src = p.src;
+    g->dst = p.dst;
+    g->n0 = (int)p.dims[0];
+    g->n1 = (int)p.dims[1];
+    g->oy0 = p.region_lo[0];
+    g->oy1 = p.region_hi[0];
+    g->ox0 = p.region_lo[1];
+    g->ox1 = p.region_hi[1];
+    g->periodic = p.boundary == STENCIL_PERIODIC;
+    g->h = (TC)p.halo;
+    g->BX = Cfg::NC - 2 * Cfg::E;
+    if (g->BX <= 0) {
+        *err = hipErrorInvalidValue;
+        return false;
+    }
+    const int W_out = g->ox1 - g->ox0, H_out = g->oy1 - g->oy0;
+    if (W_out <= 0 || H_out <= 0) return false;
+    g->nbands = (W_out + g->BX - 1) / g->BX;
     // rows per workgroup: enough tiles to fill the chip several times over
     int BY = p.tile_rows;
     if (BY <= 0) {
         const int target = 8 * (p.num_cu > 0 ? p.num_cu : 256);
-        const int segs = (target + a.nbands - 1) / a.nbands;
+        const int segs = (target + g->nbands - 1) / g->nbands;
         BY = (H_out + segs - 1) / segs;
         const int minBY = 8 * R * T > 64 ? 8 * R * T : 64;
         if (BY < minBY) BY = minBY;
         if (BY > 1024) BY = 1024;
     }
-    a.BY = BY;
-    a.nsegs = (H_out + BY - 1) / BY;
-    a.ntiles = a.nbands * a.nsegs;
-    hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, W, NT>), dim3(a.ntiles), dim3(NT), 0,
-                       stream, a);
+    g->BY = BY;
+    g->nsegs = (H_out + BY - 1) / BY;
+    g->ntiles = g->nbands * g->nsegs;
+    return true;
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T>
+hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
+{
+    using S = Valu2DShape<TS>;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W, S::NT>;
+    Valu2DArgs<TC, Cfg::K> a;
+    hipError_t err;
+    if (!valu2d_geometry<TS, TC, SHAPE, R, T>(p, &a.g, &err)) return err;
+    for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
+    hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, S::W, S::NT>), dim3(a.g.ntiles),
+                       dim3(S::NT), 0, stream, a);
+    return hipGetLastError();
+}
+
+// Batched form: n passes (one per job) of the same variant in one launch.
+// `scratch` is device memory for the job table (at least batch_bytes(n)).
+template <typename TS, typename TC, int SHAPE, int R, int T>
+hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
+{
+    using S = Valu2DShape<TS>;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W, S::NT>;
+    using Job = Valu2DBatchJob<TC, Cfg::K>;
+    std::vector<Job> jobs;
+    std::vector<int> start(1, 0);
+    jobs.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        Job j;
+        hipError_t err;
+        if (!valu2d_geometry<TS, TC, SHAPE, R, T>(ps[i], &j.g, &err)) {
+            if (err != hipSuccess) return err;
+            continue;
+        }
+        for (int k = 0; k < Cfg::K; ++k) j.w[k] = (TC)ps[i].w[k];
+        jobs.push_back(j);
+        start.push_back(start.back() + j.g.ntiles);
+    }
+    if (jobs.empty()) return hipSuccess;
+    const int nj = (int)jobs.size();
+    void *djobs = nullptr, *dstart = nullptr;
+    hipError_t e = stage->put(jobs.data(), jobs.size() * sizeof(Job), &djobs, stream);
+    if (e == hipSuccess) e = stage->put(start.data(), start.size() * sizeof(int), &dstart, stream);
+    if (e != hipSuccess) return e;
+    const int total = start.back();
+    int occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W, S::NT>, S::NT, 0);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    const int slots = occ * (ps[0].num_cu > 0 ? ps[0].num_cu : 256);
+    const int grid = total < slots ? total : slots;
+    hipLaunchKernelGGL((valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W, S::NT>), dim3(grid),
+                       dim3(S::NT), 0, stream, static_cast<const Job *>(djobs),
+                       static_cast<const int *>(dstart), nj);
     return hipGetLastError();
 }
 
 #define V2(TS, TC, DT, SH, R, T) \
-    {STENCIL_PATH_VALU, DT, SH, 2, R, T, &launch_valu2d<TS, TC, SH, R, T>}
+    {STENCIL_PATH_VALU, DT, SH, 2, R, T, &launch_valu2d<TS, TC, SH, R, T>, \
+     &launch_valu2d_batch<TS, TC, SH, R, T>}
 #define V2_T(TS, TC, DT, SH, R) \
     V2(TS, TC, DT, SH, R, 1), V2(TS, TC, DT, SH, R, 2), V2(TS, TC, DT, SH, R, 3), V2(TS, TC, DT, SH, R, 4)
 #define V2_R(TS, TC, DT, SH) V2_T(TS, TC, DT, SH, 1), V2_T(TS, TC, DT, SH, 2), V2_T(TS, TC, DT, SH, 3)

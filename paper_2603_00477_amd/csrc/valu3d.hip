@@ -363,7 +363,7 @@ hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
 }
 
 #define V3(TS, TC, DT, SH, R, T) \
-    {STENCIL_PATH_VALU, DT, SH, 3, R, T, &launch_valu3d<TS, TC, SH, R, T>}
+    {STENCIL_PATH_VALU, DT, SH, 3, R, T, &launch_valu3d<TS, TC, SH, R, T>, nullptr}
 #define V3_T(TS, TC, DT, SH, R) V3(TS, TC, DT, SH, R, 1), V3(TS, TC, DT, SH, R, 2), V3(TS, TC, DT, SH, R, 3)
 // Instantiated (shape, r, T): those that fit the register file without
 // spilling; other combinations run as single-step passes of the direct kernel.

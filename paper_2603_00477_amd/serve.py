@@ -1,0 +1,337 @@
+"""Continuous-batching server for stencil jobs on one GPU.
+
+Requests (stencil jobs of mixed shape, size and step count) arrive at any
+time.  A scheduler thread:
+
+  * admits queued jobs in arrival order while their device footprint (two
+    resident grids plus the plan's operand blocks) fits the HBM budget; a job
+    larger than the whole budget is rejected;
+  * keeps admitted grids resident on the device;
+  * runs in rounds: each round issues one pass (min(T, steps left) steps) of
+    every active job through one stencil_run_batch call, so jobs that arrive
+    while others run join the next round and their work shares launches with
+    the jobs already running;
+  * completes a job when the event recorded after its last round has fired,
+    hands its output tensor to the caller and frees its budget.
+
+Latency = completion time - arrival time.  Results are bit-identical to
+running each job alone with the same plan: the same kernels run on the same
+data in the same pass order.
+
+The executor does the device work; `GpuExecutor` drives the HIP library.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import threading
+import time
+from typing import Any, Callable, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Job:
+    shape: str
+    d: int
+    r: int
+    weights: Any
+    dims: tuple
+    steps: int
+    dtype: str = "f32"
+    boundary: str = "dirichlet"
+    halo: float = 0.0
+    T: Optional[int] = None          # None: choose by the model
+    path: Optional[str] = None       # None: the plan's resolved path
+    data: Any = None                 # host/device tensor or callable(device) -> device tensor
+    arrival: Optional[float] = None  # server clock; None = time of submit()
+    id: Any = None
+
+
+@dataclasses.dataclass
+class Done:
+    job: Job
+    output: Any
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Active:
+    __slots__ = ("job", "fut", "state", "left", "arrival", "admitted", "bytes")
+
+    def __init__(self, job, fut, state, arrival, admitted, nbytes):
+        self.job = job
+        self.fut = fut
+        self.state = state
+        self.left = int(job.steps)
+        self.arrival = arrival
+        self.admitted = admitted
+        self.bytes = nbytes
+
+
+def choose_T(stl, job, candidates=(1, 2, 3, 4)) -> int:
+    """Fusion depth with the best model prediction for the plan's path
+    (VALU), never more than the job's steps."""
+    best, best_gst = 1, -1.0
+    for T in candidates:
+        if T > max(1, job.steps):
+            break
+        m = stl.model_predict(job.shape, job.d, job.r, T, job.dtype)
+        # a larger T also pays a skirt of r*T recomputed points per tile edge
+        gst = m["gst_valu"] * (1.0 - 0.02 * job.r * T)
+        if gst > best_gst:
+            best, best_gst = T, gst
+    return best
+
+
+class GpuExecutor:
+    """Device work of the server, through the HIP library."""
+
+    def __init__(self, device="cuda", stream=None):
+        import torch
+
+        import paper_2603_00477_amd as stl
+
+        self.torch = torch
+        self.stl = stl
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.Stream(device=self.device)
+        self._plans = {}
+
+    def _plan(self, job):
+        stl = self.stl
+        T = job.T or choose_T(stl, job)
+        p = stl.Plan(job.shape, job.d, job.r, job.weights, job.dims, T=T, dtype=job.dtype,
+                     boundary=job.boundary, path=job.path, halo=job.halo)
+        return p
+
+    def footprint(self, job) -> int:
+        D = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}[job.dtype]
+        return 2 * int(np.prod(job.dims)) * D + (1 << 20)
+
+    def prepare(self, job):
+        torch = self.torch
+        plan = self._plan(job)
+        tdt = self.stl.torch_dtype(job.dtype)
+        with torch.cuda.stream(self.stream):
+            if callable(job.data):
+                a = job.data(self.device)
+            elif isinstance(job.data, torch.Tensor):
+                a = job.data.to(self.device, non_blocking=True)
+            else:
+                a = torch.as_tensor(np.asarray(job.data)).to(self.device)
+            a = a.to(tdt).contiguous()
+            b = torch.empty_like(a)
+        return {"plan": plan, "a": a, "b": b, "T": plan.info()["T"]}
+
+    def run_round(self, states, steps):
+        """One pass of every state; returns an event that fires when done."""
+        torch = self.torch
+        plans = [s["plan"] for s in states]
+        ins = [s["a"] for s in states]
+        outs = [s["b"] for s in states]
+        self.stl.run_batch(plans, ins, outs, steps, stream=self.stream)
+        for s in states:
+            s["a"], s["b"] = s["b"], s["a"]
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def pass_steps(self, state, left) -> int:
+        return min(state["T"], left)
+
+    def done(self, handle) -> bool:
+        return handle.query()
+
+    def wait(self, handle):
+        handle.synchronize()
+
+    def result(self, state):
+        return state["a"]
+
+    def release(self, state):
+        state["plan"].close()
+        state["b"] = None
+
+
+class StencilServer:
+    def __init__(self, executor, hbm_budget: int, max_inflight_rounds: int = 2,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.used = 0
+        self.clock = clock
+        self.max_inflight = max(1, int(max_inflight_rounds))
+        self._queue = collections.deque()
+        self._active = []
+        self._inflight = collections.deque()  # (handle, [finished _Active])
+        self._cv = threading.Condition()
+        self._stop = False
+        self._thread = None
+        self.rounds = 0
+        self.done = []
+
+    # ---- client side
+    def submit(self, job: Job) -> cf.Future:
+        fut = cf.Future()
+        arrival = job.arrival if job.arrival is not None else self.clock()
+        with self._cv:
+            if self._stop:
+                raise RuntimeError("server stopped")
+            self._queue.append((job, fut, arrival))
+            self._cv.notify()
+        return fut
+
+    def start(self):
+        self._thread = threading.Thread(target=self._loop, name="stencil-server", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self, drain: bool = True):
+        with self._cv:
+            if not drain:
+                while self._queue:
+                    job, fut, _ = self._queue.popleft()
+                    fut.cancel()
+            self._stop = True
+            self._cv.notify()
+        if self._thread:
+            self._thread.join()
+
+    # ---- scheduler
+    def _admit(self):
+        while self._queue:
+            job, fut, arrival = self._queue[0]
+            if fut.cancelled():
+                self._queue.popleft()
+                continue
+            try:
+                need = self.ex.footprint(job)
+            except Exception as e:  # invalid job description
+                self._queue.popleft()
+                fut.set_exception(e)
+                continue
+            if need > self.budget:
+                self._queue.popleft()
+                fut.set_exception(MemoryError(
+                    f"job needs {need} bytes, more than the whole HBM budget {self.budget}"))
+                continue
+            if self.used + need > self.budget:
+                return  # wait for running jobs to free memory (FIFO, no overtaking)
+            self._queue.popleft()
+            try:
+                state = self.ex.prepare(job)
+            except Exception as e:
+                fut.set_exception(e)
+                continue
+            self.used += need
+            self._active.append(_Active(job, fut, state, arrival, self.clock(), need))
+
+    def _finish(self, a: _Active, now: float):
+        out = self.ex.result(a.state)
+        self.ex.release(a.state)
+        self.used -= a.bytes
+        d = Done(a.job, out, a.arrival, a.admitted, now)
+        self.done.append(d)
+        a.fut.set_result(d)
+
+    def _reap(self, block: bool):
+        while self._inflight:
+            h, fin = self._inflight[0]
+            if not self.ex.done(h):
+                if not block and len(self._inflight) < self.max_inflight:
+                    return
+                self.ex.wait(h)
+            self._inflight.popleft()
+            now = self.clock()
+            for a in fin:
+                self._finish(a, now)
+            block = False
+
+    def _loop(self):
+        while True:
+            with self._cv:
+                self._reap(block=False)
+                self._admit()
+                runnable = [a for a in self._active if a.left > 0]
+                if not runnable:
+                    if self._inflight:
+                        pass  # fall through to reap below
+                    elif self._stop and not self._queue:
+                        return
+                    else:
+                        self._cv.wait(timeout=0.001)
+                        continue
+            if runnable:
+                steps = [self.ex.pass_steps(a.state, a.left) for a in runnable]
+                try:
+                    h = self.ex.run_round([a.state for a in runnable], steps)
+                except Exception:
+                    # isolate: run each job's pass alone; only jobs that fail
+                    # again are failed, the others keep their pass
+                    ok, ok_steps, h = [], [], None
+                    for a, s in zip(runnable, steps):
+                        try:
+                            h = self.ex.run_round([a.state], [s])
+                            ok.append(a)
+                            ok_steps.append(s)
+                        except Exception as e:
+                            with self._cv:
+                                self._active.remove(a)
+                                self.ex.release(a.state)
+                                self.used -= a.bytes
+                                a.fut.set_exception(e)
+                    runnable, steps = ok, ok_steps
+                    if h is None:
+                        continue
+                self.rounds += 1
+                fin = []
+                with self._cv:
+                    for a, s in zip(runnable, steps):
+                        a.left -= s
+                        if a.left <= 0:
+                            self._active.remove(a)
+                            fin.append(a)
+                    self._inflight.append((h, fin))
+            else:
+                with self._cv:
+                    self._reap(block=True)
+
+
+def latency_stats(done):
+    lat = np.array([d.latency for d in done], dtype=np.float64)
+    if lat.size == 0:
+        return {"p50_ms": None, "p99_ms": None, "n": 0}
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "n": int(lat.size)}
+
+
+def run_fifo(executor, jobs, clock=time.perf_counter, t0=None):
+    """Baseline: one plan per call, jobs run alone in arrival order, each
+    synchronised before the next starts."""
+    t0 = clock() if t0 is None else t0
+    done = []
+    for job in sorted(jobs, key=lambda j: j.arrival):
+        now = clock()
+        if job.arrival + t0 > now:
+            time.sleep(job.arrival + t0 - now)
+        st = executor.prepare(job)
+        left = int(job.steps)
+        h = None
+        while left > 0:
+            s = executor.pass_steps(st, left)
+            h = executor.run_round([st], [s])
+            left -= s
+        if h is not None:
+            executor.wait(h)
+        fin = clock()
+        done.append(Done(job, executor.result(st), job.arrival + t0, job.arrival + t0, fin))
+        executor.release(st)
+    return done

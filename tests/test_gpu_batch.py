@@ -1,0 +1,101 @@
+"""Batched runs: many grids of uneven size (and mixed variants) in one
+stencil_run_batch call give exactly the result of running each job alone,
+and match the oracle."""
+import numpy as np
+import pytest
+
+import stencil_inputs as si
+from gpu_util import case_inputs, oracle, rel_inf
+from oracle import model as omodel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_00477_amd as stl
+    stl.lib()
+    return stl
+
+
+def _jobs():
+    rng = np.random.default_rng(0)
+    jobs = []
+    # same variant (box-2D r2 T2 f32), uneven sizes -> one batched launch per round
+    for i in range(6):
+        dims = (int(rng.integers(20, 700)), int(rng.integers(20, 1500)))
+        jobs.append(("box", 2, 2, 2, "f32", dims, int(rng.integers(1, 9)), "dirichlet" if i % 2 else "periodic"))
+    # other variants mixed in, including MFMA and 3D
+    jobs += [("star", 2, 1, 3, "f64", (300, 410), 7, "dirichlet"),
+             ("star", 2, 1, 3, "f64", (33, 2000), 4, "periodic"),
+             ("box", 3, 1, 2, "f32", (20, 40, 70), 5, "periodic"),
+             ("star", 3, 2, 1, "f64", (17, 30, 50), 3, "dirichlet"),
+             ("box", 2, 3, 1, "f64", (100, 120), 0, "dirichlet")]
+    return jobs
+
+
+def test_batch_equals_alone(stl):
+    import torch
+    jobs = _jobs()
+    plans, ins, outs_b, outs_a, refs = [], [], [], [], []
+    for k, (shape, d, r, T, dt, dims, steps, bnd) in enumerate(jobs):
+        u0, u0r, t, w = case_inputs(shape, d, r, dims, dt, seed=7000 + k)
+        path = "mfma" if (k == 6) else "valu"
+        p = stl.Plan(shape, d, r, w, dims, T=T, dtype=dt, boundary=bnd, path=path)
+        plans.append(p)
+        x = t.cuda()
+        ins.append(x)
+        outs_b.append(torch.empty_like(x))
+        outs_a.append(torch.empty_like(x))
+        refs.append((shape, d, r, w, u0, steps, bnd, dt))
+    stl.run_batch(plans, ins, outs_b, [j[6] for j in jobs])
+    torch.cuda.synchronize()
+    for p, x, y, j in zip(plans, ins, outs_a, jobs):
+        p.run(x, y, j[6])
+    torch.cuda.synchronize()
+    for k in range(len(jobs)):
+        a = outs_a[k].cpu()
+        b = outs_b[k].cpu()
+        assert torch.equal(a, b), jobs[k]
+        shape, d, r, w, u0, steps, bnd, dt = refs[k]
+        ref = oracle(shape, d, r, w, u0, steps, bnd)
+        tol = 1e-12 if dt == "f64" else 1e-5
+        assert rel_inf(b.to(torch.float64).numpy(), ref) <= tol, jobs[k]
+
+
+def test_batch_repeated_calls_reuse_staging(stl):
+    """Back-to-back batch calls (the job table staging is reused)."""
+    import torch
+    w = si.normalised_weights(13, 1)
+    plans, ins, outs = [], [], []
+    for k in range(12):
+        dims = (64 + 13 * k, 200 + 7 * k)
+        plans.append(stl.Plan("star", 2, 3, w, dims, T=1, dtype="f32"))
+        ins.append(torch.rand(dims, device="cuda", dtype=torch.float32))
+        outs.append(torch.empty_like(ins[-1]))
+    ref = []
+    for p, x in zip(plans, ins):
+        y = torch.empty_like(x)
+        p.run(x, y, 3)
+        ref.append(y)
+    for _ in range(5):
+        stl.run_batch(plans, ins, outs, [3] * 12)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, outs):
+        assert torch.equal(a, b)
+
+
+def test_batch_argument_errors(stl):
+    import torch
+    w = si.normalised_weights(9, 1)
+    p = stl.Plan("box", 2, 1, w, (32, 32), T=1, dtype="f32")
+    x = torch.rand(32, 32, device="cuda")
+    with pytest.raises(stl.StencilError) as e:
+        stl.run_batch([p, p], [x, x], [torch.empty_like(x), torch.empty_like(x)], [1, 1])
+    assert e.value.status == "INVALID_ARG"
+    with pytest.raises(stl.StencilError) as e:
+        stl.run_batch([p], [x], [x], [1])
+    assert e.value.status == "ALIAS"
