@@ -242,67 +242,65 @@ class StencilServer:
         self.done.append(d)
         a.fut.set_result(d)
 
-    def _reap(self, block: bool):
-        while self._inflight:
-            h, fin = self._inflight[0]
-            if not self.ex.done(h):
-                if not block and len(self._inflight) < self.max_inflight:
-                    return
-                self.ex.wait(h)
-            self._inflight.popleft()
+    def _reap_ready(self):
+        """Finish the jobs of every completed round at the head of the queue
+        (never waits; called with the lock held)."""
+        while self._inflight and self.ex.done(self._inflight[0][0]):
+            _, fin = self._inflight.popleft()
             now = self.clock()
             for a in fin:
                 self._finish(a, now)
-            block = False
+
+    def _fail(self, a: _Active, e: Exception):
+        self._active.remove(a)
+        self.ex.release(a.state)
+        self.used -= a.bytes
+        a.fut.set_exception(e)
 
     def _loop(self):
         while True:
+            wait_on = None
             with self._cv:
-                self._reap(block=False)
+                self._reap_ready()
                 self._admit()
                 runnable = [a for a in self._active if a.left > 0]
-                if not runnable:
-                    if self._inflight:
-                        pass  # fall through to reap below
-                    elif self._stop and not self._queue:
+                if not runnable and not self._inflight:
+                    if self._stop and not self._queue:
                         return
-                    else:
-                        self._cv.wait(timeout=0.001)
-                        continue
-            if runnable:
-                steps = [self.ex.pass_steps(a.state, a.left) for a in runnable]
-                try:
-                    h = self.ex.run_round([a.state for a in runnable], steps)
-                except Exception:
-                    # isolate: run each job's pass alone; only jobs that fail
-                    # again are failed, the others keep their pass
-                    ok, ok_steps, h = [], [], None
-                    for a, s in zip(runnable, steps):
-                        try:
-                            h = self.ex.run_round([a.state], [s])
-                            ok.append(a)
-                            ok_steps.append(s)
-                        except Exception as e:
-                            with self._cv:
-                                self._active.remove(a)
-                                self.ex.release(a.state)
-                                self.used -= a.bytes
-                                a.fut.set_exception(e)
-                    runnable, steps = ok, ok_steps
-                    if h is None:
-                        continue
-                self.rounds += 1
+                    self._cv.wait(timeout=0.001)
+                    continue
+                if not runnable or len(self._inflight) >= self.max_inflight:
+                    wait_on = self._inflight[0][0]
+            if wait_on is not None:
+                self.ex.wait(wait_on)  # outside the lock: clients can submit/stop meanwhile
+                continue
+            steps = [self.ex.pass_steps(a.state, a.left) for a in runnable]
+            try:
+                h = self.ex.run_round([a.state for a in runnable], steps)
+            except Exception:
+                # isolate: run each job's pass alone; only jobs that fail
+                # again are failed, the others keep their pass
+                ok, ok_steps, h = [], [], None
+                for a, s in zip(runnable, steps):
+                    try:
+                        h = self.ex.run_round([a.state], [s])
+                        ok.append(a)
+                        ok_steps.append(s)
+                    except Exception as e:
+                        with self._cv:
+                            self._fail(a, e)
+                runnable, steps = ok, ok_steps
+                if h is None:
+                    continue
+            self.rounds += 1
+            with self._cv:
                 fin = []
-                with self._cv:
-                    for a, s in zip(runnable, steps):
-                        a.left -= s
-                        if a.left <= 0:
-                            self._active.remove(a)
-                            fin.append(a)
-                    self._inflight.append((h, fin))
-            else:
-                with self._cv:
-                    self._reap(block=True)
+                for a, s in zip(runnable, steps):
+                    a.left -= s
+                    if a.left <= 0:
+                        self._active.remove(a)
+                        fin.append(a)
+                self._inflight.append((h, fin))
 
 
 def latency_stats(done):

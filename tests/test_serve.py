@@ -20,6 +20,7 @@ class FakeExecutor:
         self.peak = 0
         self.lock = threading.Lock()
         self.order = []
+        self.device_free_at = 0.0  # rounds execute one after another, like a stream
 
     def footprint(self, job):
         if job.dims is None:
@@ -45,7 +46,9 @@ class FakeExecutor:
         self.rounds.append(ids)
         for s in states:
             s["passes"] += 1
-        return time.perf_counter() + self.pass_time * len(states)
+        start = max(time.perf_counter(), self.device_free_at)
+        self.device_free_at = start + self.pass_time * len(states)
+        return self.device_free_at
 
     def done(self, h):
         return time.perf_counter() >= h
