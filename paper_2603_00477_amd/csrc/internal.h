@@ -93,7 +93,8 @@ const std::vector<KernelEntry> &mfma2d_table_f32();
 const std::vector<KernelEntry> &mfma2d_table_bf16();
 const std::vector<KernelEntry> &mfma2d_table_f16();
 const std::vector<KernelEntry> &mfma2d_table_x3();
-const std::vector<KernelEntry> &mfma3d_kernels();
+const std::vector<KernelEntry> &mfma3d_table_f64();
+const std::vector<KernelEntry> &mfma3d_table_f32();
 std::vector<const std::vector<KernelEntry> *> all_kernel_tables();
 
 const KernelEntry *find_kernel(int path, int dtype, int shape, int d, int r, int t);

@@ -1,4 +1,4 @@
-// Registry of all kernel tables, and tables of families not built yet.
+// Registry of all kernel tables and the staging of batched job tables.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -78,17 +78,12 @@ BatchStaging::~BatchStaging()
     if (done_) (void)hipEventDestroy(done_);
 }
 
-const std::vector<KernelEntry> &mfma3d_kernels()
-{
-    static const std::vector<KernelEntry> t;
-    return t;
-}
 
 std::vector<const std::vector<KernelEntry> *> all_kernel_tables()
 {
     return {&valu2d_table_f64(),  &valu2d_table_f32(),  &valu2d_table_bf16(),
             &valu2d_table_f16(),  &valu2d_table_x3(),   &valu3d_kernels(),    &mfma2d_table_f64(),
             &mfma2d_table_f32(),  &mfma2d_table_bf16(), &mfma2d_table_f16(),
-            &mfma2d_table_x3(),   &mfma3d_kernels(),    &generic_kernels()};
+            &mfma2d_table_x3(),   &mfma3d_table_f64(),  &mfma3d_table_f32(),    &generic_kernels()};
 }
 }  // namespace stl

@@ -93,3 +93,20 @@ def test_valu2d_low_precision_storage(stl, dt, T):
     ref = oracle("box", 2, 2, w, u0r, steps, "periodic")
     passes = -(-steps // T)
     assert rel_inf(got, ref) <= passes * (U_STORE[dt] + 25 * T * 2.0 ** -24)
+
+
+CASES3 = [(shape, r, T, dt) for shape, r in (("star", 1), ("star", 2), ("box", 1)) for T in (1, 2, 3)
+          for dt in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("shape,r,T,dt", CASES3)
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+def test_mfma3d(stl, shape, r, T, dt, boundary):
+    dims = (23, 37, 70)
+    u0, u0r, t, w = case_inputs(shape, 3, r, dims, dt, seed=6400 + 10 * r + T)
+    steps = T + 1 if T > 1 else 2
+    p = stl.Plan(shape, 3, r, w, dims, T=T, dtype=dt, path="mfma", boundary=boundary, halo=0.25)
+    assert p.info()["path_name"] == "mfma"
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 3, r, w, u0, steps, boundary, 0.25)
+    assert rel_inf(got, ref) <= TOL[dt]
