@@ -1,31 +1,51 @@
 #!/usr/bin/env python3
-"""Benchmark of the stencil sweep on one MI355X.
+"""Benchmark of the stencil sweeps on one MI355X.
 
-Workload (one "step" = one whole sweep of the workload through the library):
-  Box-2D3R (49 points) and Star-2D3R (13 points), 8192 x 8192 grid, float64
-  and float32, values uniform on [0, 1), random weights normalised to sum 1,
-  zero Dirichlet halo, 100 time steps per sweep, fusion depth T in {1, 2, 4},
-  VALU and MFMA paths.  The headline line is Box-2D3R float64 at the fastest
-  (path, T); every variant is listed under "variants".
+Headline (one "step" = one whole sweep of the workload through the library):
+  Box-2D3R (49 points) and Star-2D3R (13 points), 8192 x 8192, float64 and
+  float32, U[0,1) data, random weights normalised to sum 1, zero Dirichlet
+  halo, 100 time steps per sweep, fusion depth T in {1, 2, 4}, VALU and MFMA
+  paths.  The JSON line's value is Box-2D3R float64 at the fastest (path, T).
 
-GStencil/s = grid points x time steps / seconds / 1e9, with the grids resident
-in HBM before the timed region.  Kernel time comes from HIP events recorded on
-the stream the library launches on.
+Further sections (extra keys of the same JSON line):
+  model_check  config 3 (Star-3D2R, Box-3D1R, 512^3, periodic, 50 steps,
+               T in {1,2,3}) plus the config-2 variants: the model's
+               predicted winner (VALU / tie / MFMA, tie band 0.87-1.15) next
+               to the measured one.
+  precision    config 4 (Box-2D2R, 16384^2, periodic, 1000 steps, smooth
+               sin(2 pi x) sin(2 pi y) + 1e-3 U[0,1) data): bf16 / f16 MFMA with
+               float32 accumulation, compensated bf16x3, VALU comparators;
+               relative max-norm error against the float64 GPU sweep every 100
+               steps, and GStencil/s.
+  serving      config 5 (4096 jobs, Poisson arrivals, mixed shape/d/r/size/
+               steps, float32, HBM budget): continuous-batching server vs
+               one-plan-per-call FIFO on the same trace; p50/p99 latency and
+               aggregate GStencil/s.
 
-The roofline object describes the headline variant's kernel: achieved =
-algorithmic bytes per launch (2 D per point: one read, one write) or
-algorithmic flops per launch (2 K T per point), divided by the average launch
-duration; the bound is the one the performance model assigns (HBM when the
-VALU intensity T K / D is below the ridge, otherwise the vector-ALU peak).
+GStencil/s = grid points x time steps / seconds / 1e9 (grids resident in HBM
+before the timed region).  Kernel time comes from HIP events recorded on the
+stream the library launches on.
 
-cpu_baseline: the FP64 oracle (plain C, OpenMP) timed on the host on a bounded
-sample of the same workload (a few time steps of the full grid).
+roofline (headline kernel): achieved = algorithmic bytes per launch (2 D per
+point: one read, one write) or algorithmic flops per launch (2 K T per point)
+divided by the average launch duration; the bound is the one the model
+assigns to the VALU path (HBM below the ridge T K / D < PP/BB, else the
+vector-ALU peak: 78.6 TFLOP/s FP64, 157.3 TFLOP/s FP32).  traffic: HBM bytes per launch from the
+rocprofv3 FETCH_SIZE / WRITE_SIZE summaries under profiles/, scaled by the
+same counters on a copy of known size; null when the kernel sources changed
+since those counters were taken.
+
+cpu_baseline: the FP64 oracle (plain C, OpenMP) on the host, on a bounded
+sample of the headline workload (a few time steps of the full grid).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
+import re
 import sys
 import time
 
@@ -33,10 +53,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12           # bytes/s
-PEAK_VALU_F64 = 78.6e12     # flop/s, FP64 vector FMA (256 CU x 2.4 GHz x 128)
-PEAK_VALU_F32 = 78.6e12     # flop/s, scalar FP32 FMA (packed forms not issued)
-PEAK_MFMA = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2516.6e12, "f16": 2516.6e12}
+PEAK_VALU = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 157.3e12, "f16": 157.3e12}
+# flop/s: 256 CU x 2.4 GHz x (64 FP64 | 128 FP32) FMA lanes per clock x 2
+PEAK_MFMA = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2516.6e12, "f16": 2516.6e12,
+             "bf16x3": 2516.6e12}
 DBYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}
+KERNEL_SOURCES = ["paper_2603_00477_amd/csrc/valu2d_impl.h", "paper_2603_00477_amd/csrc/valu_common.h"]
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -45,82 +71,332 @@ def parse():
     ap.add_argument("--steps", type=int, default=5, help="timed sweeps per variant")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--time-steps", type=int, default=100, help="stencil steps per sweep")
-    ap.add_argument("--n", type=int, default=8192, help="grid side")
-    ap.add_argument("--only", default="", help="comma list of variant names to run")
+    ap.add_argument("--n", type=int, default=8192, help="grid side of the headline workload")
+    ap.add_argument("--only", default="", help="comma list of headline variant names to run")
+    ap.add_argument("--sections", default="c2,c3,c4,c5")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--jobs", type=int, default=4096, help="served-stream jobs")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain device copy of the headline grid (counter calibration)")
     ap.add_argument("--json-out", default="")
     return ap.parse_args()
 
 
-def variants(n, nsteps):
+# ---------------------------------------------------------------- timing
+def timed_runs(p, x, y, nsteps, reps, warmup):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        p.run(x, y, nsteps, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        p.run(x, y, nsteps, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def roofline_for(v, info, launch_ms, npts):
+    D = DBYTES[v["dtype"]]
+    T = info["T"]
+    K = info["K"]
+    bytes_per_launch = 2.0 * D * npts
+    flops_per_launch = 2.0 * K * T * npts
+    if info["path"] == 2:  # MFMA: executed flops against the matrix peak when above its ridge
+        I_exec = T * K / D * info["gamma"] * info["alpha"] / info["S"]
+        pk = PEAK_MFMA[v["dtype"]]
+        if I_exec >= pk / PEAK_HBM:
+            ach = flops_per_launch * info["gamma"] * info["alpha"] / info["S"] / (launch_ms * 1e-3)
+            return dict(bound="mfma", achieved=ach / 1e12, peak=pk / 1e12, unit="TFLOP/s",
+                        frac=ach / pk)
+    elif T * K / D >= PEAK_VALU[v["dtype"]] / PEAK_HBM:
+        pk = PEAK_VALU[v["dtype"]]
+        ach = flops_per_launch / (launch_ms * 1e-3)
+        return dict(bound="alu", achieved=ach / 1e12, peak=pk / 1e12, unit="TFLOP/s", frac=ach / pk)
+    ach = bytes_per_launch / (launch_ms * 1e-3)
+    return dict(bound="hbm", achieved=ach / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=ach / PEAK_HBM)
+
+
+def measure(stl, v, x, w, reps, warmup):
+    import torch
+
+    try:
+        p = stl.Plan(v["shape"], v["d"], v["r"], w, v["dims"], T=v["T"], dtype=v["dtype"],
+                     path=v["path"], boundary=v.get("boundary", "dirichlet"))
+    except stl.StencilError as e:
+        return dict(error=str(e))
+    info = p.info()
+    y = torch.empty_like(x)
+    ms = timed_runs(p, x, y, v["steps"], reps, warmup)
+    npts = math.prod(v["dims"])
+    passes = -(-v["steps"] // v["T"])
+    launch_ms = ms / passes
+    out = dict(ms_per_sweep=ms, gst=npts * v["steps"] / (ms * 1e-3) / 1e9, launch_ms=launch_ms,
+               path=info["path_name"], T=info["T"], S=info["S"], alpha=info["alpha"],
+               scenario=info["scenario"], predicted_winner=info["predicted_winner"],
+               predicted_gst=info["predicted_gst_valu"] if info["path"] == 1 else info["predicted_gst_mfma"],
+               roofline=roofline_for(v, info, launch_ms, npts))
+    p.close()
+    del y
+    return out
+
+
+def verdict(ratio):
+    return "mfma" if ratio > 1.15 else ("valu" if ratio < 0.87 else "tie")
+
+
+# ---------------------------------------------------------------- config 2
+def headline_variants(n, nsteps):
     out = []
     for shape, K in (("box", 49), ("star", 13)):
         for dt in ("f64", "f32"):
             for T in (1, 2, 4):
                 for path in ("valu", "mfma"):
-                    name = f"{shape}-2d3r-{dt}-T{T}-{path}"
-                    out.append(dict(name=name, shape=shape, K=K, d=2, r=3, dtype=dt, T=T,
-                                    path=path, dims=(n, n), steps=nsteps))
+                    out.append(dict(name=f"{shape}-2d3r-{dt}-T{T}-{path}", shape=shape, K=K, d=2, r=3,
+                                    dtype=dt, T=T, path=path, dims=(n, n), steps=nsteps))
     return out
 
 
-def time_variant(stl, v, x, w, steps, warmup):
+def section_c2(stl, args):
     import torch
 
-    try:
-        p = stl.Plan(v["shape"], v["d"], v["r"], w, v["dims"], T=v["T"], dtype=v["dtype"],
-                     path=v["path"])
-    except stl.StencilError as e:
-        return dict(error=str(e))
-    info = p.info()
-    y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        p.run(x, y, v["steps"], stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        p.run(x, y, v["steps"], stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    npts = v["dims"][0] * v["dims"][1]
-    gst = npts * v["steps"] / (ms * 1e-3) / 1e9
-    passes = (v["steps"] + v["T"] - 1) // v["T"]
-    launch_ms = ms / passes
-    D = DBYTES[v["dtype"]]
-    bytes_per_launch = 2.0 * D * npts
-    flops_per_launch = 2.0 * v["K"] * v["T"] * npts
-    # model bound of the VALU path: HBM below the ridge, vector ALU above it
-    peak_alu = PEAK_VALU_F64 if v["dtype"] == "f64" else PEAK_VALU_F32
-    I = v["T"] * v["K"] / D
-    if I < peak_alu / PEAK_HBM:
-        roof = dict(bound="hbm", achieved=bytes_per_launch / (launch_ms * 1e-3) / 1e9,
-                    peak=PEAK_HBM / 1e9, unit="GB/s")
-    else:
-        roof = dict(bound="alu", achieved=flops_per_launch / (launch_ms * 1e-3) / 1e12,
-                    peak=peak_alu / 1e12, unit="TFLOP/s")
-    if info["path"] == 2:  # MFMA path: useful flops against the matrix peak
-        I_exec = I * info["gamma"] * info["alpha"] / info["S"]
-        pk = PEAK_MFMA[v["dtype"]]
-        if I_exec >= pk / PEAK_HBM:
-            roof = dict(bound="mfma", achieved=flops_per_launch * info["gamma"] * info["alpha"] /
-                        info["S"] / (launch_ms * 1e-3) / 1e12, peak=pk / 1e12, unit="TFLOP/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    p.close()
-    return dict(ms_per_sweep=ms, gst=gst, launch_ms=launch_ms, passes=passes, roofline=roof,
-                path=info["path_name"], predicted_gst=info["predicted_gst_valu"] if info["path"] == 1
-                else info["predicted_gst_mfma"], predicted_winner=info["predicted_winner"],
-                scenario=info["scenario"], S=info["S"], alpha=info["alpha"])
+    import stencil_inputs as si
+
+    n = args.n
+    vs = headline_variants(n, args.time_steps)
+    if args.only:
+        keep = set(args.only.split(","))
+        vs = [v for v in vs if v["name"] in keep]
+    u0 = si.uniform_grid((n, n), seed=si.data_seed(2, 0))
+    inputs, results = {}, {}
+    for v in vs:
+        if v["dtype"] not in inputs:
+            inputs[v["dtype"]] = si.round_to(u0, v["dtype"])[1].to("cuda")
+        w = si.normalised_weights(v["K"], seed=si.weight_seed(2, 0 if v["shape"] == "box" else 1))
+        r = measure(stl, v, inputs[v["dtype"]], w, args.steps, args.warmup)
+        results[v["name"]] = r
+        log(f"{v['name']}: " + (f"{r['gst']:.1f} GSt/s, {r['roofline']['frac']:.3f} of "
+                                 f"{r['roofline']['bound']}" if "gst" in r else r.get("error", "?")))
+    if args.calib_copy:
+        x = inputs.get("f64", next(iter(inputs.values())))
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {x.numel() * x.element_size()} bytes read and written per copy")
+    del inputs
+    torch.cuda.empty_cache()
+    return results
 
 
-def cpu_baseline(n, budget_s):
-    """Oracle on the full grid for as many time steps as fit the budget."""
+# ---------------------------------------------------------------- config 3
+def section_c3(stl, args):
+    import torch
+
+    import stencil_inputs as si
+
+    n = 512
+    res = {}
+    u0 = si.uniform_grid((n, n, n), seed=si.data_seed(3, 0))
+    for dt in ("f64", "f32"):
+        x = si.round_to(u0, dt)[1].to("cuda")
+        for vi, (shape, r, K) in enumerate((("star", 2, 13), ("box", 1, 27))):
+            w = si.normalised_weights(K, seed=si.weight_seed(3, vi))
+            for T in (1, 2, 3):
+                row = {}
+                for path in ("valu", "mfma"):
+                    v = dict(shape=shape, K=K, d=3, r=r, dtype=dt, T=T, path=path, dims=(n, n, n),
+                             steps=50, boundary="periodic")
+                    row[path] = measure(stl, v, x, w, 2, 1)
+                name = f"{shape}-3d{r}r-{dt}-T{T}"
+                res[name] = row
+                log(f"{name}: " + ", ".join(f"{k} {v_.get('gst', float('nan')):.1f}" for k, v_ in row.items()))
+        del x
+        torch.cuda.empty_cache()
+    return res
+
+
+def model_check(c2, c3):
+    rows = []
+    pairs = {}
+    for name, r in c2.items():
+        if "gst" not in r:
+            continue
+        key = name.rsplit("-", 1)[0]
+        pairs.setdefault(key, {})[r["path"]] = r
+    for key, row in list(pairs.items()) + [(k, v) for k, v in c3.items()]:
+        if "gst" not in row.get("valu", {}) or "gst" not in row.get("mfma", {}):
+            continue
+        pred = {-1: "valu", 0: "tie", 1: "mfma"}[row["valu"]["predicted_winner"]]
+        ratio = row["mfma"]["gst"] / row["valu"]["gst"]
+        rows.append(dict(case=key, predicted=pred, measured=verdict(ratio), ratio=ratio,
+                         scenario=row["valu"]["scenario"], valu_gst=row["valu"]["gst"],
+                         mfma_gst=row["mfma"]["gst"], S=row["mfma"]["S"], alpha=row["mfma"]["alpha"]))
+    agree = sum(r["predicted"] == r["measured"] for r in rows)
+    return dict(cases=rows, agree=agree, total=len(rows))
+
+
+# ---------------------------------------------------------------- config 4
+def section_c4(stl, args):
     import numpy as np
+    import torch
 
+    import stencil_inputs as si
+
+    n = 16384
+    u0 = si.smooth_grid((n, n), seed=si.data_seed(4, 0))
+    w = si.normalised_weights(25, seed=si.weight_seed(4, 0))
+    npts = n * n
+
+    def sweep(dtype, path, T, x0):
+        p = stl.Plan("box", 2, 2, w, (n, n), T=T, dtype=dtype, path=path, boundary="periodic")
+        x = x0.clone()
+        y = torch.empty_like(x)
+        snaps, ms_total = [], 0.0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(10):
+            e0.record()
+            p.run(x, y, 100)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_total += e0.elapsed_time(e1)
+            x, y = y, x
+            snaps.append(x)
+            x = x.clone()
+        p.close()
+        return snaps, ms_total
+
+    ref0 = torch.from_numpy(u0).to("cuda")
+    ref_snaps, ref_ms = sweep("f64", "valu", 2, ref0)
+    log(f"f64 reference: {npts * 1000 / (ref_ms * 1e-3) / 1e9:.1f} GSt/s")
+    out = {"reference": dict(dtype="f64", path="valu", T=2, gst=npts * 1000 / (ref_ms * 1e-3) / 1e9)}
+    modes = [("bf16", "mfma", 4), ("f16", "mfma", 4), ("bf16x3", "mfma", 4), ("bf16", "mfma", 2),
+             ("bf16", "valu", 2), ("f16", "valu", 2), ("f32", "valu", 2), ("f32", "mfma", 4)]
+    for dt, path, T in modes:
+        x0 = si.round_to(u0, dt)[1].to("cuda")
+        try:
+            snaps, ms = sweep(dt, path, T, x0)
+        except stl.StencilError as e:
+            out[f"{dt}-{path}-T{T}"] = dict(error=str(e))
+            continue
+        errs = []
+        for k, (s, rsnap) in enumerate(zip(snaps, ref_snaps)):
+            d = (s.to(torch.float64) - rsnap)
+            errs.append(float(d.abs().max() / rsnap.abs().max()))
+            del d
+        m = stl.model_predict("box", 2, 2, T, dt)
+        out[f"{dt}-{path}-T{T}"] = dict(gst=npts * 1000 / (ms * 1e-3) / 1e9, err_every_100=errs,
+                                        predicted_winner=m["winner"], scenario=m["scenario"],
+                                        predicted_gst=m["gst_valu"] if path == "valu" else m["gst_mfma"])
+        log(f"{dt}-{path}-T{T}: {out[f'{dt}-{path}-T{T}']['gst']:.1f} GSt/s, err@1000 {errs[-1]:.2e}")
+        del snaps, x0
+        torch.cuda.empty_cache()
+    del ref_snaps, ref0
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------- config 5
+def _served_jobs(stl, trace, scale_arrivals=1.0):
+    import torch
+
+    import stencil_inputs as si
+    from paper_2603_00477_amd.serve import Job
+
+    jobs = []
+    for t in trace:
+        K = (2 * t["r"] + 1) ** t["d"] if t["shape"] == "box" else 2 * t["d"] * t["r"] + 1
+        w = si.normalised_weights(K, t["weight_seed"])
+        seed = t["data_seed"]
+
+        def gen(device, dims=t["dims"], seed=seed):
+            g = torch.Generator(device=device)
+            g.manual_seed(seed)
+            return torch.rand(dims, generator=g, device=device, dtype=torch.float32)
+
+        jobs.append(Job(t["shape"], t["d"], t["r"], w, t["dims"], t["steps"], dtype="f32",
+                        boundary=t["boundary"], data=gen, arrival=t["arrival"] * scale_arrivals,
+                        id=t["id"]))
+    return jobs
+
+
+def _serve(ex, jobs, t0, budget):
+    """Submit each job at its arrival time to a fresh server; returns timing
+    records (outputs are dropped as soon as they arrive)."""
+    import time as _t
+
+    from paper_2603_00477_amd.serve import StencilServer
+
+    srv = StencilServer(ex, hbm_budget=budget).start()
+    futs = []
+    for j in jobs:
+        now = _t.perf_counter() - t0
+        if j.arrival > now:
+            _t.sleep(j.arrival - now)
+        j.arrival = None
+        f = srv.submit(j)
+        f.add_done_callback(lambda f: setattr(f.result(), "output", None) if not f.exception() else None)
+        futs.append(f)
+    for f in futs:
+        f.result()
+    srv.stop()
+    return srv.done, srv.rounds
+
+
+def section_serving(stl, args):
+    import torch
+
+    import stencil_inputs as si
+    from paper_2603_00477_amd.serve import GpuExecutor, latency_stats, run_fifo
+
+    budget = 32 << 30
+    trace = si.served_trace(args.jobs, seed=5000, rate_per_s=1.0)
+    work = sum(math.prod(t["dims"]) * t["steps"] for t in trace)
+    ex = GpuExecutor()
+    out = dict(jobs=len(trace), point_steps=work, hbm_budget=budget)
+    # capacity: every job available at t = 0
+    for mode in ("fifo", "served"):
+        jobs = _served_jobs(stl, trace, scale_arrivals=0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "fifo":
+            done = run_fifo(ex, jobs, t0=t0, keep_outputs=False)
+        else:
+            done, rounds = _serve(ex, jobs, t0, budget)
+        span = max(d.finished for d in done) - t0
+        out[f"{mode}_capacity"] = dict(jobs_per_s=len(jobs) / span, gst=work / span / 1e9, makespan_s=span)
+        log(f"serving capacity {mode}: {len(jobs) / span:.1f} jobs/s, {work / span / 1e9:.1f} GSt/s")
+        torch.cuda.empty_cache()
+    # Poisson arrivals at 0.8 x the one-plan-per-call capacity (trace drawn at
+    # rate 1/s, arrival times rescaled)
+    rate = 0.8 * out["fifo_capacity"]["jobs_per_s"]
+    out["arrival_rate_jobs_per_s"] = rate
+    for mode in ("served", "fifo"):
+        jobs = _served_jobs(stl, trace, scale_arrivals=1.0 / rate)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "fifo":
+            done = run_fifo(ex, jobs, t0=t0, keep_outputs=False)
+        else:
+            done, rounds = _serve(ex, jobs, t0, budget)
+            out["rounds"] = rounds
+        span = max(d.finished for d in done) - t0
+        st = latency_stats(done)
+        out[mode] = dict(p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
+                         gst=work / span / 1e9, makespan_s=span)
+        log(f"serving {mode} at 0.8 load: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+            f"{work / span / 1e9:.1f} GSt/s")
+        torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------- CPU baseline / traffic
+def cpu_baseline(n, budget_s):
     import stencil_inputs as si
     from oracle import core
 
@@ -129,8 +405,7 @@ def cpu_baseline(n, budget_s):
     threads = core.max_threads()
     t0 = time.perf_counter()
     core.run("box", 2, 3, w, u0, 1, "dirichlet", 0.0)
-    t1 = time.perf_counter()
-    one = t1 - t0
+    one = time.perf_counter() - t0
     k = max(1, min(20, int(budget_s / max(one, 1e-3)) - 1))
     t0 = time.perf_counter()
     core.run("box", 2, 3, w, u0, k, "dirichlet", 0.0)
@@ -139,70 +414,83 @@ def cpu_baseline(n, budget_s):
                 sample=f"Box-2D3R f64 {n}x{n}, {k} time steps (of 100), zero Dirichlet halo")
 
 
+def source_hash():
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def recorded_traffic(variant):
+    """HBM bytes per launch recorded under profiles/ for `variant`, if the
+    kernel sources still hash to the recorded value."""
+    path = os.path.join(ROOT, "profiles", "traffic_valu2d_box2d3r_8192.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"sources_sha1:\s*([0-9a-f]+)", txt)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(rf"^\|\s*{re.escape(variant)}\s*\|\s*([0-9.eE+]+)\s*\|", txt, re.M)
+    return float(m.group(1)) if m else None
+
+
+# ---------------------------------------------------------------- main
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the stencil library has no multi-GPU path "
-              "(a grid would shard as slabs along its slowest axis with r*T-deep halo "
+              "(a grid would shard as slabs along its slowest axis with an r*T-deep halo "
               "exchange per pass); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
     import paper_2603_00477_amd as stl
-    import stencil_inputs as si
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     stl.lib()
-    n = args.n
-    vs = variants(n, args.time_steps)
-    if args.only:
-        keep = set(args.only.split(","))
-        vs = [v for v in vs if v["name"] in keep]
-    u0 = si.uniform_grid((n, n), seed=si.data_seed(2, 0))
-    inputs = {}
-    results = {}
-    for v in vs:
-        key = v["dtype"]
-        if key not in inputs:
-            inputs[key] = si.round_to(u0, key)[1].to("cuda")
-        w = si.normalised_weights(v["K"], seed=si.weight_seed(2, 0 if v["shape"] == "box" else 1))
-        r = time_variant(stl, v, inputs[key], w, args.steps, args.warmup)
-        results[v["name"]] = r
-        print(f"# {v['name']}: " + (f"{r['gst']:.1f} GSt/s, {r['roofline']['frac']:.3f} of "
-              f"{r['roofline']['bound']}" if "gst" in r else r.get("error", "?")), file=sys.stderr,
-              flush=True)
-    ok = {k: r for k, r in results.items() if "gst" in r}
+    sections = set(args.sections.split(","))
+    c2 = section_c2(stl, args) if "c2" in sections else {}
+    ok = {k: r for k, r in c2.items() if "gst" in r}
     box64 = {k: r for k, r in ok.items() if k.startswith("box-2d3r-f64")}
-    head_name = max(box64 or ok, key=lambda k: (box64 or ok)[k]["gst"])
-    head = ok[head_name]
-    hv = next(v for v in vs if v["name"] == head_name)
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(n, args.cpu_seconds)
+    pool = box64 or ok
+    head_name = max(pool, key=lambda k: pool[k]["gst"]) if pool else None
+    c3 = section_c3(stl, args) if "c3" in sections else {}
+    c4 = section_c4(stl, args) if "c4" in sections else None
+    c5 = section_serving(stl, args) if "c5" in sections else None
+    cpu = None if args.no_cpu or not head_name else cpu_baseline(args.n, args.cpu_seconds)
+    head = ok.get(head_name, {})
+    hv = next((v for v in headline_variants(args.n, args.time_steps) if v["name"] == head_name), None)
+    roof = dict(head.get("roofline", {}))
+    if roof:
+        roof["traffic"] = recorded_traffic(head_name)
     line = {
         "metric": "GStencil/s (Box-2D3R 8192^2 f64, 100 steps, best path/T)",
-        "value": head["gst"],
+        "value": head.get("gst"),
         "unit": "GStencil/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_sweep"],
+        "ms_per_step": head.get("ms_per_sweep"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": hv["dtype"],
+        "dtype": hv["dtype"] if hv else None,
         "data": "synthetic",
-        "config": {"workload": f"{hv['shape'].capitalize()}-2D3R {n}x{n} {hv['dtype']}, "
-                               f"{args.time_steps} steps, Dirichlet h=0, T={hv['T']}, "
-                               f"{head['path']} path",
-                   "grid": [n, n], "time_steps": args.time_steps, "T": hv["T"],
-                   "path": head["path"]},
-        "roofline": dict(head["roofline"], traffic=None),
+        "config": {"workload": (f"Box-2D3R {args.n}x{args.n} {hv['dtype']}, {args.time_steps} steps, "
+                                f"Dirichlet h=0, T={hv['T']}, {head['path']} path") if hv else None,
+                   "grid": [args.n, args.n], "time_steps": args.time_steps,
+                   "T": hv["T"] if hv else None, "path": head.get("path")},
+        "roofline": roof or None,
         "cpu_baseline": cpu,
-        "variants": {k: {kk: r[kk] for kk in ("gst", "path", "predicted_gst", "predicted_winner",
-                                               "scenario", "launch_ms")}
-                     | {"frac": r["roofline"]["frac"], "bound": r["roofline"]["bound"]}
+        "variants": {k: {"gst": r["gst"], "path": r["path"], "T": r["T"], "frac": r["roofline"]["frac"],
+                         "bound": r["roofline"]["bound"], "predicted_gst": r["predicted_gst"],
+                         "scenario": r["scenario"], "launch_ms": r["launch_ms"]}
                      for k, r in ok.items()},
+        "model_check": model_check(c2, c3) if (c2 or c3) else None,
+        "precision": c4,
+        "serving": c5,
     }
     s = json.dumps(line)
     print(s, flush=True)

@@ -144,6 +144,21 @@ int stencil_run(stencil_plan_t plan, const void *in, void *out, int64_t steps, v
 int stencil_run_batch(int n, const stencil_plan_t *plans, const void *const *ins,
                       void *const *outs, const int64_t *steps, void *stream);
 
+/*
+ * Autotuner: choose the plan's path, fusion depth T and VALU rows per
+ * workgroup.  Every runnable (path, T <= min(4, steps)) is ranked by the
+ * roofline model (stencil_model_predict); the best `max_candidates` are timed
+ * on `in` -> `out` (probe runs of up to two passes, HIP events on `stream`,
+ * the call blocks until they finish) and the fastest is applied to the plan.
+ * Results are cached per (shape, d, r, dtype, boundary, dims) for the process:
+ * a later call for the same problem applies the cached choice without timing.
+ * `out` is overwritten with an unspecified result; `in` is read only.
+ * *best_gst (optional) receives the measured GStencil/s of the choice.
+ * Errors: INVALID_ARG, ALIAS, UNSUPPORTED (nothing runnable), HIP.
+ */
+int stencil_plan_autotune(stencil_plan_t plan, const void *in, void *out, int64_t steps,
+                          int max_candidates, void *stream, double *best_gst);
+
 /* Release a plan and its device memory.  Call only after the stream that ran
  * it has drained.  NULL is ignored. */
 void stencil_plan_destroy(stencil_plan_t plan);
@@ -211,6 +226,17 @@ typedef struct {
  */
 int stencil_model_predict(const stencil_model_in_t *in, const stencil_hw_t *hw,
                           stencil_model_out_t *out);
+
+/*
+ * Measured ceilings for the model (the call blocks; HIP events on `stream`):
+ *   kind 0: HBM copy bandwidth, bytes/s, over `buf` (device, `bytes` >= 8 KiB,
+ *           a multiple of 32: first half copied to the second half)
+ *   kind 1: FP64 vector FMA, kind 2: FP32 scalar vector FMA (flop/s)
+ *   kind 3: MFMA f64 16x16x4, kind 4: MFMA f32 16x16x4,
+ *   kind 5: MFMA bf16 16x16x32 (flop/s); `buf` unused for kinds 1-5.
+ * Errors: INVALID_ARG, OOM, HIP.
+ */
+int stencil_microbench(int kind, void *buf, int64_t bytes, void *stream, double *result);
 
 /* Sparsity factor S of this library's MFMA operand layout for the T-step
  * composite of (shape, d, r) in dtype: useful MACs / executed MACs.

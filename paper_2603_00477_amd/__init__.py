@@ -94,6 +94,18 @@ class Plan:
                                 _stream_handle(stream)), "stencil_run")
         return out
 
+    def autotune(self, inp, out, steps, max_candidates=4, stream=None) -> float:
+        """Choose path, T and tile rows by timing model-ranked candidates on
+        inp -> out (out is overwritten).  Returns the measured GStencil/s."""
+        self._check_tensor(inp, "in")
+        self._check_tensor(out, "out")
+        g = ctypes.c_double()
+        check(lib().stencil_plan_autotune(self._h, ctypes.c_void_p(inp.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), int(steps),
+                                          int(max_candidates), _stream_handle(stream),
+                                          ctypes.byref(g)), "stencil_plan_autotune")
+        return g.value
+
     def close(self):
         if self._h is not None and self._h.value:
             lib().stencil_plan_destroy(self._h)
@@ -148,6 +160,20 @@ def model_predict(shape, d, r, T, dtype, S=0.0, alpha=0.0, sparse=False, hw=None
     check(lib().stencil_model_predict(ctypes.byref(mi), hwp, ctypes.byref(mo)),
           "stencil_model_predict")
     return {f: getattr(mo, f) for f, _ in _abi.ModelOut._fields_}
+
+
+def microbench(kind: str, nbytes: int = 1 << 30) -> float:
+    """Measured ceiling: 'copy' (bytes/s), 'fma_f64', 'fma_f32', 'mfma_f64',
+    'mfma_f32', 'mfma_bf16' (flop/s)."""
+    import torch
+
+    kinds = ["copy", "fma_f64", "fma_f32", "mfma_f64", "mfma_f32", "mfma_bf16"]
+    k = kinds.index(kind)
+    buf = torch.empty(nbytes if k == 0 else 32, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_double()
+    check(lib().stencil_microbench(k, ctypes.c_void_p(buf.data_ptr()), int(buf.numel()),
+                                   _stream_handle(None), ctypes.byref(out)), "stencil_microbench")
+    return out.value
 
 
 def mfma_sparsity(shape, d, r, T, dtype) -> float:

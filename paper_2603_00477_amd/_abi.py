@@ -20,7 +20,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALIAS", 4: "OOM", 5: 
 
 SYMBOLS = ["stencil_plan", "stencil_plan_set", "stencil_plan_info", "stencil_run",
            "stencil_run_batch", "stencil_plan_destroy", "stencil_last_error", "stencil_compose",
-           "stencil_hw_default", "stencil_model_predict", "stencil_mfma_sparsity"]
+           "stencil_hw_default", "stencil_model_predict", "stencil_mfma_sparsity",
+           "stencil_plan_autotune", "stencil_microbench"]
 
 
 class PlanInfo(ctypes.Structure):
@@ -85,9 +86,13 @@ def lib():
     L.stencil_hw_default.argtypes = [ctypes.c_int, ctypes.POINTER(HW)]
     L.stencil_model_predict.argtypes = [ctypes.POINTER(ModelIn), ctypes.POINTER(HW),
                                         ctypes.POINTER(ModelOut)]
+    L.stencil_plan_autotune.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, dp]
+    L.stencil_microbench.argtypes = [ctypes.c_int, vp, i64, vp, dp]
+    L.stencil_microbench.restype = ctypes.c_int
     L.stencil_mfma_sparsity.argtypes = [ctypes.c_int] * 5
     L.stencil_mfma_sparsity.restype = ctypes.c_double
     for name in ("stencil_plan", "stencil_plan_set", "stencil_plan_info", "stencil_run",
+                 "stencil_plan_autotune",
                  "stencil_run_batch", "stencil_compose", "stencil_hw_default",
                  "stencil_model_predict"):
         getattr(L, name).restype = ctypes.c_int

@@ -22,7 +22,10 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics",
+          # the streaming kernels rely on full unrolling of their row loops
+          # (rotating register accumulators); never fall back to a partial unroll
+          "-mllvm", "-pragma-unroll-threshold=1000000"]
 
 
 def sources():
@@ -43,12 +46,25 @@ def _compile(src: str) -> str:
     return warn
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(src: str) -> bool:
+    obj = os.path.join(BUILD, src + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "stencil.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int | None = None, verbose: bool = False, force: bool = True) -> str:
+    """Compile and link the library.  force=False recompiles only translation
+    units older than their source or any header."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    todo = srcs if force else [s for s in srcs if _stale(s)]
+    jobs = jobs or min(max(1, len(todo)), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, s): s for s in srcs}
+        futs = {ex.submit(_compile, s): s for s in todo}
         for f in cf.as_completed(futs):
             w = f.result()
             if verbose and w:
@@ -62,4 +78,4 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--inc" not in sys.argv))

@@ -45,6 +45,7 @@ struct PassArgs {
     const void *afrag_lo;    // compensated mode: lo parts
     int R;                   // MFMA composite radius (r * steps)
     int num_cu;
+    int slots_per_cu;        // resident workgroups per CU of the launched kernel (0 = unknown)
 };
 
 // Device copies of small host tables (job lists of batched launches).  put()

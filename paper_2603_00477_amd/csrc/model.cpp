@@ -101,14 +101,14 @@ extern "C" int stencil_hw_default(int dtype, stencil_hw_t *out)
         h.PP_mfma_sparse = 78.6e12;
         break;
     case STENCIL_F32:
-        h.PP_valu = 78.6e12;   // scalar v_fma_f32 (packed FP32 forms are not issued)
+        h.PP_valu = 157.3e12;  // FP32 vector (scalar v_fma_f32 issues at twice the FP64 rate)
         h.PP_mfma = 157.3e12;  // FP32 matrix
         h.PP_mfma_sparse = 157.3e12;
         break;
     case STENCIL_BF16:
     case STENCIL_F16:
     case STENCIL_F32_BF16X3:
-        h.PP_valu = 78.6e12;   // FP32 arithmetic on the vector path
+        h.PP_valu = 157.3e12;  // FP32 arithmetic on the vector path
         h.PP_mfma = 2516.6e12; // dense BF16/FP16 matrix
         h.PP_mfma_sparse = 5033.2e12;
         break;

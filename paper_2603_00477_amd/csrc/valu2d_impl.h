@@ -3,20 +3,22 @@
 // C grows by t, M stays 2D per point because intermediates stay on chip).
 //
 // Work decomposition
-//   A workgroup of NT threads owns a column band of NC = NT*W columns (each
-//   thread W consecutive columns) and streams down a segment of rows.  Of the
-//   NC columns, E = roundup(R*T, W) on each side are the skirt that later steps
-//   consume; the band's valid output width is BX = NC - 2E.
+//   Every wave is independent: it owns a column band of 64*W columns (each
+//   lane W consecutive columns) and streams down a segment of rows.  Of the
+//   band, E = roundup(R*T, W) columns on each side are the skirt that later
+//   steps consume; the valid output width is BX = 64W - 2E.  There is no LDS
+//   and no barrier: neighbour columns come from cross-lane permutes.
 //
-// Step pipeline (one barrier per row)
-//   Stage 0 loads input row k (prefetched U rows ahead into registers) and
-//   writes it to an LDS row buffer.  Stage s = 1..T reads the row that stage
-//   s-1 wrote one iteration earlier (double-buffered by iteration parity),
-//   scatters it into 2R+1 rotating accumulator rows per thread column
-//   (input-stationary: input row i adds w[a][.] to output row i-a), and emits
-//   the completed output row i-R: to LDS for the next stage, or to HBM for
-//   stage T.  Contributions to an output arrive in canonical order (kernel row
-//   a ascending, column b ascending).
+// Step pipeline
+//   Stage 0 takes input row k (prefetched U rows ahead into registers).
+//   Stage s = 1..T consumes the row stage s-1 produced one iteration earlier,
+//   as a (W + 2R)-column window assembled by permutes at the end of that
+//   iteration (so the permute latency overlaps the next row's arithmetic).
+//   It scatters the window into 2R+1 rotating accumulator rows per lane
+//   column (input-stationary: input row i adds w[a][.] to output row i-a) and
+//   emits the completed output row i-R: to the next stage, or to HBM for
+//   stage T.  Contributions to an output arrive in canonical order (kernel
+//   row a ascending, column b ascending).
 //
 // Boundaries
 //   Dirichlet: every field, intermediate ones included, is h outside the grid
@@ -55,13 +57,13 @@ struct Valu2DArgs {
     TC w[K];
 };
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
+constexpr int kValu2DWaves = 4;  // waves per workgroup (independent bands)
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W>
 struct Valu2DCfg {
     static constexpr int K = SHAPE == STENCIL_BOX ? (2 * R + 1) * (2 * R + 1) : 4 * R + 1;
-    static constexpr int NC = NT * W;
-    static constexpr int E = ((R * T + W - 1) / W) * W;
-    static constexpr int PADL = ((R + W - 1) / W) * W;
-    static constexpr int LROW = NC + 2 * PADL;
+    static constexpr int NCW = 64 * W;                     // columns per wave
+    static constexpr int E = ((R * T + W - 1) / W) * W;    // skirt per side
     static constexpr int Q = 2 * R + 1;
     // rows prefetched ahead: a multiple of Q, at least 4
     static constexpr int U = Q * ((4 + Q - 1) / Q);
@@ -74,22 +76,50 @@ __device__ __forceinline__ int star_axis_index(int axis, int off)
     return 1 + axis * 2 * R + (off < 0 ? off + R : off + R - 1);
 }
 
-// One tile (column band x row segment) of one pass.  `wk` holds the weights,
-// `lds` the stage row buffers; the caller provides both.
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
-__device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
-                                            const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K],
-                                            int tile,
-                                            TC (&lds)[T][2][Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::LROW])
+// value of `v` in lane (addr / 4) mod 64 (ds_bpermute: LDS crossbar, no storage)
+__device__ __forceinline__ float lane_read(float v, int addr)
 {
-    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_read(double v, int addr)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// win[j] = column lane*W - R + j of the wave's row, from the lanes' own W
+// values (edge lanes receive wrapped values; those columns lie in the skirt).
+template <typename TC, int W, int R>
+__device__ __forceinline__ void assemble_window(const TC (&own)[W], TC (&win)[W + 2 * R], int lane)
+{
+#pragma unroll
+    for (int j = 0; j < W; ++j) win[R + j] = own[j];
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {  // column lane*W - m
+        const int dl = -((m + W - 1) / W);
+        const int je = -m - dl * W;
+        win[R - m] = lane_read(own[je], (lane + dl) * 4);
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) {  // column lane*W + W + m
+        const int t = W + m;
+        win[R + W + m] = lane_read(own[t % W], (lane + t / W) * 4);
+    }
+}
+
+// One tile (column band x row segment) of one pass, run by one wave.
+template <typename TS, typename TC, int SHAPE, int R, int T, int W>
+__device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
+                                            const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W>::K],
+                                            int tile, int lane)
+{
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W>;
     constexpr int Q = Cfg::Q;
     constexpr int U = Cfg::U;
-    constexpr int LROW = Cfg::LROW;
-    constexpr int PADL = Cfg::PADL;
     using Vec = RawVec<TS, W>;
 
-    const int tid = threadIdx.x;
     const int band = tile / a.nsegs;
     const int seg = tile - band * a.nsegs;
     const int x0 = a.ox0 + band * a.BX;
@@ -97,7 +127,7 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
     const int y1 = min(y0 + a.BY, a.oy1);
     const int BYe = y1 - y0;
     const int xe = min(x0 + a.BX, a.ox1);
-    const int cb = x0 - Cfg::E + tid * W;  // first column owned by this thread
+    const int cb = x0 - Cfg::E + lane * W;  // first column owned by this lane
 
     const TS *src = static_cast<const TS *>(a.src);
     TS *dst = static_cast<TS *>(a.dst);
@@ -105,10 +135,6 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
     const bool periodic = a.periodic != 0;
     const TC h = a.h;
 
-    // zero the LDS pads (never written by the pipeline)
-    for (int i = tid; i < T * 2 * LROW; i += NT) (&lds[0][0][0])[i] = TC(0);
-
-    // per-column facts
     bool col_in[W];
     int col_src[W];
     bool col_store[W];
@@ -133,6 +159,12 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < W; ++j) acc[s][q][j] = TC(0);
+    // input windows of stages 1..T (the previous iteration's rows)
+    TC wins[T][W + 2 * R];
+#pragma unroll
+    for (int s = 0; s < T; ++s)
+#pragma unroll
+        for (int j = 0; j < W + 2 * R; ++j) wins[s][j] = TC(0);
 
     auto load_row = [&](int k, Vec &v) {
         const int i = ybase + k;
@@ -157,58 +189,48 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
 #pragma unroll
     for (int u = 0; u < U; ++u)
         if (u < KTOT) load_row(u, ring[u]);
-    __syncthreads();
 
     for (int kb = 0; kb < KTOT; kb += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = kb + u;
             if (k >= KTOT) break;
-            const int par = k & 1;
-            // ---- stage 0: input row -> LDS, prefetch U rows ahead
-            {
-                TC *w0 = &lds[0][par][PADL + tid * W];
+            TC outs[T][W];  // rows completed at this iteration by stages 0..T-1
+            // ---- stage 0: input row, prefetch U rows ahead
 #pragma unroll
-                for (int j = 0; j < W; ++j) w0[j] = to_compute<TC>(ring[u].e[j]);
-                if (k + U < KTOT) load_row(k + U, ring[u]);
-            }
+            for (int j = 0; j < W; ++j) outs[0][j] = to_compute<TC>(ring[u].e[j]);
+            if (k + U < KTOT) load_row(k + U, ring[u]);
             // ---- stages 1..T
 #pragma unroll
             for (int s = 1; s <= T; ++s) {
                 const bool active = k >= s + 2 * R * (s - 1) && k < BYe + 2 * R * T + s;
                 const int qc = u % Q;  // slot completing at this iteration
+                if (s < T) {
+#pragma unroll
+                    for (int j = 0; j < W; ++j) outs[s][j] = TC(0);
+                }
                 if (active) {
-                    const TC *rb = &lds[s - 1][par ^ 1][PADL - R + tid * W];
-                    TC win[W + 2 * R];
+                    const TC *win = wins[s - 1];
 #pragma unroll
-                    for (int j = 0; j < W + 2 * R; ++j) win[j] = rb[j];
+                    for (int bo = -R; bo <= R; ++bo) {
 #pragma unroll
-                    for (int ao = -R; ao <= R; ++ao) {
-                        const int q = ((u - ao + R) % Q + Q) % Q;
-                        if (SHAPE == STENCIL_BOX) {
-#pragma unroll
-                            for (int bo = -R; bo <= R; ++bo) {
+                        for (int ao = -R; ao <= R; ++ao) {
+                            const int q = ((u - ao + R) % Q + Q) % Q;
+                            if (SHAPE == STENCIL_BOX) {
                                 const TC wv = wk[(ao + R) * (2 * R + 1) + (bo + R)];
 #pragma unroll
                                 for (int j = 0; j < W; ++j)
                                     acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
-                            }
-                        } else {
-                            if (ao != 0) {
+                            } else if (ao != 0 && bo == 0) {
                                 const TC wv = wk[star_axis_index<SHAPE, R>(0, ao)];
 #pragma unroll
                                 for (int j = 0; j < W; ++j)
                                     acc[s - 1][q][j] = fma_c(wv, win[j + R], acc[s - 1][q][j]);
-                            } else {
+                            } else if (ao == 0) {
+                                const TC wv = bo == 0 ? wk[0] : wk[star_axis_index<SHAPE, R>(1, bo)];
 #pragma unroll
-                                for (int bo = -R; bo <= R; ++bo) {
-                                    const TC wv = bo == 0 ? wk[0]
-                                                          : wk[star_axis_index<SHAPE, R>(1, bo)];
-#pragma unroll
-                                    for (int j = 0; j < W; ++j)
-                                        acc[s - 1][q][j] =
-                                            fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
-                                }
+                                for (int j = 0; j < W; ++j)
+                                    acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
                             }
                         }
                     }
@@ -224,9 +246,8 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                             for (int j = 0; j < W; ++j)
                                 if (!(row_in && col_in[j])) outv[j] = h;
                         }
-                        TC *wr = &lds[s][par][PADL + tid * W];
 #pragma unroll
-                        for (int j = 0; j < W; ++j) wr[j] = outv[j];
+                        for (int j = 0; j < W; ++j) outs[s][j] = outv[j];
                     } else if (yo >= y0 && yo < y1) {
                         TS *rowp = dst + (int64_t)yo * n1;
                         Vec ov;
@@ -247,7 +268,9 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
 #pragma unroll
                 for (int j = 0; j < W; ++j) acc[s - 1][qc][j] = TC(0);
             }
-            __syncthreads();
+            // ---- windows for the next iteration (permute latency overlaps it)
+#pragma unroll
+            for (int s = 0; s < T; ++s) assemble_window<TC, W, R>(outs[s], wins[s], lane);
         }
     }
 }
@@ -265,18 +288,18 @@ __device__ __forceinline__ void load_weights(TC (&wk)[K], const SrcT *w)
     }
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
-__global__ __launch_bounds__(NT) void valu2d_kernel(
-    Valu2DArgs<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K> a)
+template <typename TS, typename TC, int SHAPE, int R, int T, int W>
+__global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_kernel(
+    Valu2DArgs<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W>::K> a)
 {
-    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
-    __shared__ TC lds[T][2][Cfg::LROW];
-    // XCD-aware tile order: blocks that land on one XCD take consecutive tiles
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W>;
+    // XCD-aware order: the workgroups resident on one XCD take consecutive
+    // tiles (consecutive row segments of a band share halo rows in its L2)
+    const int tile = xcd_remap(blockIdx.x, gridDim.x) * kValu2DWaves + (int)(threadIdx.x >> 6);
     if (tile >= a.g.ntiles) return;
     TC wk[Cfg::K];
     load_weights(wk, a.w);
-    valu2d_tile<TS, TC, SHAPE, R, T, W, NT>(a.g, wk, tile, lds);
+    valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, tile, threadIdx.x & 63);
 }
 
 // One job of a batched launch: geometry plus weights.
@@ -286,33 +309,33 @@ struct Valu2DBatchJob {
     TC w[K];
 };
 
-// Persistent batched launch: the workgroups walk one list of (job, tile)
-// items spanning every job of the batch (jobs of uneven sizes), item i owned
-// by workgroup i mod gridDim.  tile_start[j] is the first item of job j
-// (tile_start[njobs] = total).
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int NT>
-__global__ __launch_bounds__(NT) void valu2d_batch_kernel(
-    const Valu2DBatchJob<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>::K> *jobs,
+// Persistent batched launch: the waves walk one list of (job, tile) items
+// spanning every job of the batch (jobs of uneven sizes).  Wave w of
+// workgroup b takes items (b + i*gridDim)*waves + w.  tile_start[j] is the
+// first item of job j (tile_start[njobs] = total).
+template <typename TS, typename TC, int SHAPE, int R, int T, int W>
+__global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
+    const Valu2DBatchJob<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W>::K> *jobs,
     const int *tile_start, int njobs)
 {
-    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W, NT>;
-    __shared__ TC lds[T][2][Cfg::LROW];
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W>;
     const int total = tile_start[njobs];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int j = 0;
-    for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
+    for (int wg = xcd_remap(blockIdx.x, gridDim.x);; wg += gridDim.x) {
+        const int item = wg * kValu2DWaves + wave;
+        if (item >= total) break;
         while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
         const Valu2DJob<TC> g = jobs[j].g;
         TC wk[Cfg::K];
         load_weights(wk, jobs[j].w);
-        valu2d_tile<TS, TC, SHAPE, R, T, W, NT>(g, wk, item - tile_start[j], lds);
-        __syncthreads();
+        valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, item - tile_start[j], lane);
     }
 }
 
 template <typename TS>
 struct Valu2DShape {
     static constexpr int W = 16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS);
-    static constexpr int NT = 256;
 };
 
 // Fill the geometry of one pass; returns false when there is nothing to do.
@@ -320,7 +343,7 @@ template <typename TS, typename TC, int SHAPE, int R, int T>
 bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
 {
     using S = Valu2DShape<TS>;
-    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W, S::NT>;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     *err = hipSuccess;
     g->src = p.src;
     g->dst = p.dst;
@@ -332,7 +355,7 @@ bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
     g->ox1 = p.region_hi[1];
     g->periodic = p.boundary == STENCIL_PERIODIC;
     g->h = (TC)p.halo;
-    g->BX = Cfg::NC - 2 * Cfg::E;
+    g->BX = Cfg::NCW - 2 * Cfg::E;
     if (g->BX <= 0) {
         *err = hipErrorInvalidValue;
         return false;
@@ -340,15 +363,21 @@ bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
     const int W_out = g->ox1 - g->ox0, H_out = g->oy1 - g->oy0;
     if (W_out <= 0 || H_out <= 0) return false;
     g->nbands = (W_out + g->BX - 1) / g->BX;
-    // rows per workgroup: enough tiles to fill the chip several times over
+    // rows per wave: the wave count is a whole number of waves of the resident
+    // slots (waves per CU x CUs), as few rounds as keep segments long enough to
+    // amortise the 2rT + T pipeline rows
     int BY = p.tile_rows;
     if (BY <= 0) {
-        const int target = 8 * (p.num_cu > 0 ? p.num_cu : 256);
-        const int segs = (target + g->nbands - 1) / g->nbands;
+        const int slots = (p.num_cu > 0 ? p.num_cu : 256) * (p.slots_per_cu > 0 ? p.slots_per_cu : 8);
+        const int minBY = 16 * (2 * R * T + T) > 64 ? 16 * (2 * R * T + T) : 64;
+        int segs = 1;
+        for (int rounds = 1; rounds <= 64; ++rounds) {
+            segs = (rounds * slots) / g->nbands;
+            if (segs < 1) segs = 1;
+            if ((H_out + segs - 1) / segs <= 4 * minBY) break;
+        }
         BY = (H_out + segs - 1) / segs;
-        const int minBY = 8 * R * T > 64 ? 8 * R * T : 64;
-        if (BY < minBY) BY = minBY;
-        if (BY > 1024) BY = 1024;
+        if (BY < 16) BY = 16;
     }
     g->BY = BY;
     g->nsegs = (H_out + BY - 1) / BY;
@@ -360,23 +389,32 @@ template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
 {
     using S = Valu2DShape<TS>;
-    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W, S::NT>;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     Valu2DArgs<TC, Cfg::K> a;
     hipError_t err;
-    if (!valu2d_geometry<TS, TC, SHAPE, R, T>(p, &a.g, &err)) return err;
+    static const int occ = [] {  // resident waves per CU of this instance
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, valu2d_kernel<TS, TC, SHAPE, R, T, S::W>,
+                                                         64 * kValu2DWaves, 0) != hipSuccess || o < 1)
+            o = 2;
+        return o * kValu2DWaves;
+    }();
+    PassArgs q = p;
+    q.slots_per_cu = occ;
+    if (!valu2d_geometry<TS, TC, SHAPE, R, T>(q, &a.g, &err)) return err;
     for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
-    hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, S::W, S::NT>), dim3(a.g.ntiles),
-                       dim3(S::NT), 0, stream, a);
+    const int grid = (a.g.ntiles + kValu2DWaves - 1) / kValu2DWaves;
+    hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, S::W>), dim3(grid), dim3(64 * kValu2DWaves), 0,
+                       stream, a);
     return hipGetLastError();
 }
 
 // Batched form: n passes (one per job) of the same variant in one launch.
-// `scratch` is device memory for the job table (at least batch_bytes(n)).
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
     using S = Valu2DShape<TS>;
-    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W, S::NT>;
+    using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     using Job = Valu2DBatchJob<TC, Cfg::K>;
     std::vector<Job> jobs;
     std::vector<int> start(1, 0);
@@ -398,15 +436,15 @@ hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
     hipError_t e = stage->put(jobs.data(), jobs.size() * sizeof(Job), &djobs, stream);
     if (e == hipSuccess) e = stage->put(start.data(), start.size() * sizeof(int), &dstart, stream);
     if (e != hipSuccess) return e;
-    const int total = start.back();
+    const int total_wg = (start.back() + kValu2DWaves - 1) / kValu2DWaves;
     int occ = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W, S::NT>, S::NT, 0);
+        &occ, valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W>, 64 * kValu2DWaves, 0);
     if (e != hipSuccess || occ < 1) occ = 1;
     const int slots = occ * (ps[0].num_cu > 0 ? ps[0].num_cu : 256);
-    const int grid = total < slots ? total : slots;
-    hipLaunchKernelGGL((valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W, S::NT>), dim3(grid),
-                       dim3(S::NT), 0, stream, static_cast<const Job *>(djobs),
+    const int grid = total_wg < slots ? total_wg : slots;
+    hipLaunchKernelGGL((valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W>), dim3(grid),
+                       dim3(64 * kValu2DWaves), 0, stream, static_cast<const Job *>(djobs),
                        static_cast<const int *>(dstart), nj);
     return hipGetLastError();
 }

@@ -358,8 +358,11 @@ template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
 {
     constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
-    constexpr int WY = (R * T >= 6) ? 4 : 2;
-    return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, 16>(p, stream);
+    // box r = 3 (343 weights, read from LDS): one row per thread, 32 thread rows
+    constexpr bool big_box = SHAPE == STENCIL_BOX && R >= 3;
+    constexpr int WY = big_box ? 1 : ((R * T >= 6) ? 4 : 2);
+    constexpr int TY = big_box ? 32 : 16;
+    return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, TY>(p, stream);
 }
 
 #define V3(TS, TC, DT, SH, R, T) \
@@ -379,6 +382,8 @@ const std::vector<KernelEntry> &valu3d_kernels()
     static const std::vector<KernelEntry> table = {
         V3_S(double, double, STENCIL_F64),
         V3_S(float, float, STENCIL_F32),
+        // box r = 3 in float32 only (float64 would spill; it runs on the direct kernel)
+        V3(float, float, STENCIL_F32, STENCIL_BOX, 3, 1),
     };
     return table;
 }
