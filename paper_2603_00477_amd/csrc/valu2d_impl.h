@@ -46,7 +46,8 @@ struct Valu2DJob {
     void *dst;
     int n0, n1;
     int oy0, oy1, ox0, ox1;
-    int BX, BY, nbands, nsegs, ntiles;
+    int BX, BY, nbands, nsegs;
+    int nwg;  // workgroup items: ceil(nbands / waves) band groups x nsegs segments
     int periodic;
     TC h;
 };
@@ -113,15 +114,13 @@ __device__ __forceinline__ void assemble_window(const TC (&own)[W], TC (&win)[W 
 template <typename TS, typename TC, int SHAPE, int R, int T, int W>
 __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                                             const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W>::K],
-                                            int tile, int lane)
+                                            int band, int seg, int lane)
 {
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W>;
     constexpr int Q = Cfg::Q;
     constexpr int U = Cfg::U;
     using Vec = RawVec<TS, W>;
 
-    const int band = tile / a.nsegs;
-    const int seg = tile - band * a.nsegs;
     const int x0 = a.ox0 + band * a.BX;
     const int y0 = a.oy0 + seg * a.BY;
     const int y1 = min(y0 + a.BY, a.oy1);
@@ -195,20 +194,17 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
         for (int u = 0; u < U; ++u) {
             const int k = kb + u;
             if (k >= KTOT) break;
-            TC outs[T][W];  // rows completed at this iteration by stages 0..T-1
-            // ---- stage 0: input row, prefetch U rows ahead
+            // Stages run from T down to 1 so that the window each one produces
+            // for the next stage can be assembled at once (its consumer has
+            // already used the previous window this iteration); the permute
+            // latency then hides behind the lower stages' arithmetic.
 #pragma unroll
-            for (int j = 0; j < W; ++j) outs[0][j] = to_compute<TC>(ring[u].e[j]);
-            if (k + U < KTOT) load_row(k + U, ring[u]);
-            // ---- stages 1..T
-#pragma unroll
-            for (int s = 1; s <= T; ++s) {
+            for (int s = T; s >= 1; --s) {
                 const bool active = k >= s + 2 * R * (s - 1) && k < BYe + 2 * R * T + s;
                 const int qc = u % Q;  // slot completing at this iteration
-                if (s < T) {
+                TC outv[W];
 #pragma unroll
-                    for (int j = 0; j < W; ++j) outs[s][j] = TC(0);
-                }
+                for (int j = 0; j < W; ++j) outv[j] = TC(0);
                 if (active) {
                     const TC *win = wins[s - 1];
 #pragma unroll
@@ -234,9 +230,8 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                             }
                         }
                     }
-                    // emit the completed row
+                    // the completed row
                     const int yo = ybase + k - s * (1 + R);  // row completed by stage s
-                    TC outv[W];
 #pragma unroll
                     for (int j = 0; j < W; ++j) outv[j] = acc[s - 1][qc][j];
                     if (s < T) {
@@ -246,8 +241,6 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                             for (int j = 0; j < W; ++j)
                                 if (!(row_in && col_in[j])) outv[j] = h;
                         }
-#pragma unroll
-                        for (int j = 0; j < W; ++j) outs[s][j] = outv[j];
                     } else if (yo >= y0 && yo < y1) {
                         TS *rowp = dst + (int64_t)yo * n1;
                         Vec ov;
@@ -267,10 +260,17 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                 }
 #pragma unroll
                 for (int j = 0; j < W; ++j) acc[s - 1][qc][j] = TC(0);
+                // window of this stage's row for stage s+1 at the next iteration
+                if (s < T) assemble_window<TC, W, R>(outv, wins[s], lane);
             }
-            // ---- windows for the next iteration (permute latency overlaps it)
+            // ---- stage 0: input row (window for stage 1), prefetch U rows ahead
+            {
+                TC inrow[W];
 #pragma unroll
-            for (int s = 0; s < T; ++s) assemble_window<TC, W, R>(outs[s], wins[s], lane);
+                for (int j = 0; j < W; ++j) inrow[j] = to_compute<TC>(ring[u].e[j]);
+                if (k + U < KTOT) load_row(k + U, ring[u]);
+                assemble_window<TC, W, R>(inrow, wins[0], lane);
+            }
         }
     }
 }
@@ -293,13 +293,17 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_kernel(
     Valu2DArgs<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W>::K> a)
 {
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W>;
-    // XCD-aware order: the workgroups resident on one XCD take consecutive
-    // tiles (consecutive row segments of a band share halo rows in its L2)
-    const int tile = xcd_remap(blockIdx.x, gridDim.x) * kValu2DWaves + (int)(threadIdx.x >> 6);
-    if (tile >= a.g.ntiles) return;
+    // The waves of a workgroup take adjacent bands of one row segment (their
+    // skirt columns are read together); XCD-aware order: the workgroups
+    // resident on one XCD take consecutive segments of a band group (which
+    // share halo rows in that XCD's L2).
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g >= a.g.nwg) return;
+    const int band = (g / a.g.nsegs) * kValu2DWaves + (int)(threadIdx.x >> 6);
+    if (band >= a.g.nbands) return;
     TC wk[Cfg::K];
     load_weights(wk, a.w);
-    valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, tile, threadIdx.x & 63);
+    valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, band, g % a.g.nsegs, threadIdx.x & 63);
 }
 
 // One job of a batched launch: geometry plus weights.
@@ -309,10 +313,10 @@ struct Valu2DBatchJob {
     TC w[K];
 };
 
-// Persistent batched launch: the waves walk one list of (job, tile) items
-// spanning every job of the batch (jobs of uneven sizes).  Wave w of
-// workgroup b takes items (b + i*gridDim)*waves + w.  tile_start[j] is the
-// first item of job j (tile_start[njobs] = total).
+// Persistent batched launch: the workgroups walk one list of (job, band
+// group x segment) items spanning every job of the batch (jobs of uneven
+// sizes); workgroup b takes items b + i*gridDim.  tile_start[j] is the first
+// item of job j (tile_start[njobs] = total).
 template <typename TS, typename TC, int SHAPE, int R, int T, int W>
 __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
     const Valu2DBatchJob<TC, Valu2DCfg<TS, TC, SHAPE, R, T, W>::K> *jobs,
@@ -322,14 +326,15 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
     const int total = tile_start[njobs];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int j = 0;
-    for (int wg = xcd_remap(blockIdx.x, gridDim.x);; wg += gridDim.x) {
-        const int item = wg * kValu2DWaves + wave;
-        if (item >= total) break;
+    for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
         const Valu2DJob<TC> g = jobs[j].g;
+        const int local = item - tile_start[j];
+        const int band = (local / g.nsegs) * kValu2DWaves + wave;
+        if (band >= g.nbands) continue;
         TC wk[Cfg::K];
         load_weights(wk, jobs[j].w);
-        valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, item - tile_start[j], lane);
+        valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, band, local % g.nsegs, lane);
     }
 }
 
@@ -370,9 +375,10 @@ bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
     if (BY <= 0) {
         const int slots = (p.num_cu > 0 ? p.num_cu : 256) * (p.slots_per_cu > 0 ? p.slots_per_cu : 8);
         const int minBY = 16 * (2 * R * T + T) > 64 ? 16 * (2 * R * T + T) : 64;
+        const int groups = (g->nbands + kValu2DWaves - 1) / kValu2DWaves;
         int segs = 1;
         for (int rounds = 1; rounds <= 64; ++rounds) {
-            segs = (rounds * slots) / g->nbands;
+            segs = (rounds * slots) / (groups * kValu2DWaves);
             if (segs < 1) segs = 1;
             if ((H_out + segs - 1) / segs <= 4 * minBY) break;
         }
@@ -381,7 +387,7 @@ bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
     }
     g->BY = BY;
     g->nsegs = (H_out + BY - 1) / BY;
-    g->ntiles = g->nbands * g->nsegs;
+    g->nwg = ((g->nbands + kValu2DWaves - 1) / kValu2DWaves) * g->nsegs;
     return true;
 }
 
@@ -403,7 +409,7 @@ hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
     q.slots_per_cu = occ;
     if (!valu2d_geometry<TS, TC, SHAPE, R, T>(q, &a.g, &err)) return err;
     for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
-    const int grid = (a.g.ntiles + kValu2DWaves - 1) / kValu2DWaves;
+    const int grid = a.g.nwg;
     hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, S::W>), dim3(grid), dim3(64 * kValu2DWaves), 0,
                        stream, a);
     return hipGetLastError();
@@ -428,7 +434,7 @@ hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
         }
         for (int k = 0; k < Cfg::K; ++k) j.w[k] = (TC)ps[i].w[k];
         jobs.push_back(j);
-        start.push_back(start.back() + j.g.ntiles);
+        start.push_back(start.back() + j.g.nwg);
     }
     if (jobs.empty()) return hipSuccess;
     const int nj = (int)jobs.size();
@@ -436,7 +442,7 @@ hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
     hipError_t e = stage->put(jobs.data(), jobs.size() * sizeof(Job), &djobs, stream);
     if (e == hipSuccess) e = stage->put(start.data(), start.size() * sizeof(int), &dstart, stream);
     if (e != hipSuccess) return e;
-    const int total_wg = (start.back() + kValu2DWaves - 1) / kValu2DWaves;
+    const int total_wg = start.back();
     int occ = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &occ, valu2d_batch_kernel<TS, TC, SHAPE, R, T, S::W>, 64 * kValu2DWaves, 0);
