@@ -60,12 +60,20 @@ public:
     ~BatchStaging();
 
 private:
-    hipError_t grow(size_t need, hipStream_t stream);
-    uint8_t *host_ = nullptr;
-    uint8_t *dev_ = nullptr;
-    size_t cap_ = 0, used_ = 0;
-    hipEvent_t done_ = nullptr;
-    bool pending_ = false;
+    // A ring of pinned-host / device buffer pairs: one batch call fills one
+    // slot, so up to kSlots batches can be queued on the device before a new
+    // call has to wait for the oldest to finish with its slot.
+    static constexpr int kSlots = 4;
+    struct Slot {
+        uint8_t *host = nullptr;
+        uint8_t *dev = nullptr;
+        size_t cap = 0, used = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    hipError_t grow(Slot &s, size_t need, hipStream_t stream);
+    Slot slots_[kSlots];
+    int cur_ = kSlots - 1;
 };
 
 // One launchable kernel variant.

@@ -431,6 +431,13 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
     BatchStaging &stage = stages[dev];
     hipError_t e = stage.begin(stream);
     if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batch staging: ") + hipGetErrorString(e));
+    // the slot is marked busy until the stream passes this point, also when a
+    // launch below fails after earlier ones were queued
+    struct SlotRelease {
+        BatchStaging &s;
+        hipStream_t st;
+        ~SlotRelease() { (void)s.end(st); }
+    } release{stage, stream};
 
     std::vector<std::vector<PassDesc>> sched((size_t)n);
     size_t rounds = 0;
@@ -478,8 +485,6 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
             if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(e));
         }
     }
-    e = stage.end(stream);
-    if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batch staging: ") + hipGetErrorString(e));
     return STENCIL_OK;
 }
 

@@ -10,21 +10,25 @@ namespace stl {
 hipError_t BatchStaging::begin(hipStream_t stream)
 {
     (void)stream;
-    if (pending_) {
-        hipError_t e = hipEventSynchronize(done_);
+    cur_ = (cur_ + 1) % kSlots;
+    Slot &s = slots_[cur_];
+    if (s.pending) {
+        // the batch that last used this slot may still read its tables
+        hipError_t e = hipEventSynchronize(s.done);
         if (e != hipSuccess) return e;
-        pending_ = false;
+        s.pending = false;
     }
-    used_ = 0;
+    s.used = 0;
     return hipSuccess;
 }
 
-hipError_t BatchStaging::grow(size_t need, hipStream_t stream)
+hipError_t BatchStaging::grow(Slot &s, size_t need, hipStream_t stream)
 {
-    // regions handed out in this call may still be read by queued kernels
+    // regions of this slot handed out in this call may still be read by
+    // kernels already queued
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
-    size_t cap = cap_ ? cap_ : (size_t)1 << 16;
+    size_t cap = s.cap ? s.cap : (size_t)1 << 16;
     while (cap < need) cap *= 2;
     uint8_t *h = nullptr, *d = nullptr;
     e = hipHostMalloc((void **)&h, cap, hipHostMallocDefault);
@@ -34,48 +38,52 @@ hipError_t BatchStaging::grow(size_t need, hipStream_t stream)
         (void)hipHostFree(h);
         return e;
     }
-    if (host_) (void)hipHostFree(host_);
-    if (dev_) (void)hipFree(dev_);
-    host_ = h;
-    dev_ = d;
-    cap_ = cap;
-    used_ = 0;
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    s.host = h;
+    s.dev = d;
+    s.cap = cap;
+    s.used = 0;
     return hipSuccess;
 }
 
 hipError_t BatchStaging::put(const void *host, size_t bytes, void **dev, hipStream_t stream)
 {
-    const size_t off = (used_ + 255) & ~(size_t)255;
-    if (off + bytes > cap_) {
-        hipError_t e = grow(off + bytes > 2 * cap_ ? off + bytes : 2 * cap_, stream);
+    Slot &s = slots_[cur_];
+    const size_t off = (s.used + 255) & ~(size_t)255;
+    if (off + bytes > s.cap) {
+        hipError_t e = grow(s, off + bytes > 2 * s.cap ? off + bytes : 2 * s.cap, stream);
         if (e != hipSuccess) return e;
         return put(host, bytes, dev, stream);
     }
-    std::memcpy(host_ + off, host, bytes);
-    hipError_t e = hipMemcpyAsync(dev_ + off, host_ + off, bytes, hipMemcpyHostToDevice, stream);
+    std::memcpy(s.host + off, host, bytes);
+    hipError_t e = hipMemcpyAsync(s.dev + off, s.host + off, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return e;
-    used_ = off + bytes;
-    *dev = dev_ + off;
+    s.used = off + bytes;
+    *dev = s.dev + off;
     return hipSuccess;
 }
 
 hipError_t BatchStaging::end(hipStream_t stream)
 {
-    if (!done_) {
-        hipError_t e = hipEventCreateWithFlags(&done_, hipEventDisableTiming);
+    Slot &s = slots_[cur_];
+    if (!s.done) {
+        hipError_t e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = hipEventRecord(done_, stream);
-    if (e == hipSuccess) pending_ = true;
+    hipError_t e = hipEventRecord(s.done, stream);
+    if (e == hipSuccess) s.pending = true;
     return e;
 }
 
 BatchStaging::~BatchStaging()
 {
     // process teardown: the runtime may already be gone, errors are ignored
-    if (host_) (void)hipHostFree(host_);
-    if (dev_) (void)hipFree(dev_);
-    if (done_) (void)hipEventDestroy(done_);
+    for (Slot &s : slots_) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
 }
 
 
