@@ -243,6 +243,14 @@ int stencil_microbench(int kind, void *buf, int64_t bytes, void *stream, double 
  * Returns a value in (0, 1], or a negative value on invalid arguments. */
 double stencil_mfma_sparsity(int shape, int d, int r, int T, int dtype);
 
+/* Whether this library has a kernel that fuses T steps of (shape, d, r) in
+ * one pass of `path` (STENCIL_PATH_VALU or STENCIL_PATH_MFMA) for `dtype`.
+ * Plans may ask for any T; a depth without a fused kernel runs as T passes
+ * of one step (same result, T times the traffic), so callers that choose T
+ * themselves (the server, autotuners) use this to keep to fused depths.
+ * Host-only, thread-safe.  Returns 1 or 0; 0 also for invalid arguments. */
+int stencil_kernel_available(int path, int dtype, int shape, int d, int r, int T);
+
 #ifdef __cplusplus
 }
 #endif

@@ -176,6 +176,12 @@ def microbench(kind: str, nbytes: int = 1 << 30) -> float:
     return out.value
 
 
+def kernel_available(path, dtype, shape, d, r, T) -> bool:
+    """True when a kernel fuses T steps of (shape, d, r) on `path` for dtype."""
+    return bool(lib().stencil_kernel_available(_code(PATHS, path), _code(DTYPES, dtype),
+                                               _code(SHAPES, shape), int(d), int(r), int(T)))
+
+
 def mfma_sparsity(shape, d, r, T, dtype) -> float:
     return float(lib().stencil_mfma_sparsity(_code(SHAPES, shape), int(d), int(r), int(T),
                                              _code(DTYPES, dtype)))

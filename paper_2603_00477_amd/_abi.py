@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALIAS", 4: "OOM", 5: 
 SYMBOLS = ["stencil_plan", "stencil_plan_set", "stencil_plan_info", "stencil_run",
            "stencil_run_batch", "stencil_plan_destroy", "stencil_last_error", "stencil_compose",
            "stencil_hw_default", "stencil_model_predict", "stencil_mfma_sparsity",
-           "stencil_plan_autotune", "stencil_microbench"]
+           "stencil_plan_autotune", "stencil_microbench", "stencil_kernel_available"]
 
 
 class PlanInfo(ctypes.Structure):
@@ -91,6 +91,8 @@ def lib():
     L.stencil_microbench.restype = ctypes.c_int
     L.stencil_mfma_sparsity.argtypes = [ctypes.c_int] * 5
     L.stencil_mfma_sparsity.restype = ctypes.c_double
+    L.stencil_kernel_available.argtypes = [ctypes.c_int] * 6
+    L.stencil_kernel_available.restype = ctypes.c_int
     for name in ("stencil_plan", "stencil_plan_set", "stencil_plan_info", "stencil_run",
                  "stencil_plan_autotune",
                  "stencil_run_batch", "stencil_compose", "stencil_hw_default",

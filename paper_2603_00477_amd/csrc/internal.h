@@ -50,8 +50,9 @@ struct PassArgs {
 
 // Device copies of small host tables (job lists of batched launches).  put()
 // copies `bytes` into a pinned host region and enqueues its upload on
-// `stream`; regions handed out since begin() stay valid until the next
-// begin(), which first waits for the previous call's uploads to finish.
+// `stream`.  Each begin() .. end() bracket (one batch call) fills one slot of
+// a ring; its regions stay valid until the slot comes round again, and
+// begin() waits only if the batch that last used that slot is still queued.
 class BatchStaging {
 public:
     hipError_t begin(hipStream_t stream);
@@ -96,6 +97,7 @@ const std::vector<KernelEntry> &valu2d_table_bf16();
 const std::vector<KernelEntry> &valu2d_table_f16();
 const std::vector<KernelEntry> &valu2d_table_x3();  // float storage, FP64 arithmetic
 const std::vector<KernelEntry> &valu3d_kernels();
+const std::vector<KernelEntry> &valu3d_box_kernels();  // boxes r >= 2, one step per pass
 const std::vector<KernelEntry> &generic_kernels();
 const std::vector<KernelEntry> &mfma2d_table_f64();
 const std::vector<KernelEntry> &mfma2d_table_f32();

@@ -498,6 +498,14 @@ bool overlap(const void *a, const void *b, size_t n)
 
 extern "C" const char *stencil_last_error(void) { return g_last_error.c_str(); }
 
+extern "C" int stencil_kernel_available(int path, int dtype, int shape, int d, int r, int T)
+{
+    if ((path != STENCIL_PATH_VALU && path != STENCIL_PATH_MFMA) || !valid_dtype(dtype) ||
+        (shape != STENCIL_STAR && shape != STENCIL_BOX) || (d != 2 && d != 3) || r < 1 || T < 1)
+        return 0;
+    return find_kernel(path, dtype, shape, d, r, T) != nullptr ? 1 : 0;
+}
+
 extern "C" int stencil_compose(int shape, int d, int r, const double *weights, int T, double *out,
                                int *k_t)
 {

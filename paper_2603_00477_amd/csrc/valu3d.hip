@@ -13,8 +13,8 @@
 // barrier per plane.
 //
 // Weights: a set of up to 48 dwords lives in scalar registers, up to 64
-// dwords is pinned in vector registers, larger sets (box r >= 2) are read from
-// LDS with uniform addresses.
+// dwords is pinned in vector registers.  Boxes with r >= 2 (125 or 343
+// weights) run on the one-step kernel of valu3d_box.hip.
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
@@ -52,7 +52,8 @@ struct Valu3DCfg {
     static constexpr int PLANE = LROWS * LDX;
     static constexpr int Q = 2 * R + 1;
     static constexpr int U = Q;                             // planes prefetched ahead
-    static constexpr int WMODE = sizeof(TC) * K <= 192 ? 0 : (sizeof(TC) * K <= 256 ? 1 : 2);
+    static constexpr int WMODE = sizeof(TC) * K <= 192 ? 0 : 1;
+    static_assert(sizeof(TC) * K <= 256, "large boxes run on the one-step box kernel");
 };
 
 template <int R>
@@ -77,7 +78,6 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
     using Vec = RawVec<TS, W>;
 
     __shared__ TC lds[T][2][PLANE];
-    __shared__ TC wl[WMODE == 2 ? K : 1];
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -104,21 +104,14 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
     const TS hs = to_storage<TS>(h);
 
     for (int i = tid; i < T * 2 * PLANE; i += NT) (&lds[0][0][0])[i] = TC(0);
-    if constexpr (WMODE == 2)
-        for (int i = tid; i < K; i += NT) wl[i] = a.w[i];
 
-    TC wk[WMODE == 2 ? 1 : K];
-    if constexpr (WMODE != 2) {
+    TC wk[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            wk[k] = a.w[k];
-            if constexpr (WMODE == 1) asm volatile("" : "+v"(wk[k]));
-        }
+    for (int k = 0; k < K; ++k) {
+        wk[k] = a.w[k];
+        if constexpr (WMODE == 1) asm volatile("" : "+v"(wk[k]));
     }
-    auto weight = [&](int k) -> TC {
-        if constexpr (WMODE == 2) return wl[k];
-        else return wk[k];
-    };
+    auto weight = [&](int k) -> TC { return wk[k]; };
 
     bool col_in[W], col_store[W];
     int col_src[W];
@@ -210,7 +203,6 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
                 const bool active = k >= s + 2 * R * (s - 1) && k < BZe + 2 * R * T + s;
                 const int qc = u % Q;
                 if (active) {
-                    if constexpr (WMODE == 2) asm volatile("" ::: "memory");
                     const TC *rb = &lds[s - 1][par ^ 1][lpos - R * LDX - R];
                     // stream the (WY+2R) x (W+2R) neighbourhood one LDS row at a time
 #pragma unroll
@@ -358,11 +350,8 @@ template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
 {
     constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
-    // box r = 3 (343 weights, read from LDS): one row per thread, 32 thread rows
-    constexpr bool big_box = SHAPE == STENCIL_BOX && R >= 3;
-    constexpr int WY = big_box ? 1 : ((R * T >= 6) ? 4 : 2);
-    constexpr int TY = big_box ? 32 : 16;
-    return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, TY>(p, stream);
+    constexpr int WY = (R * T >= 6) ? 4 : 2;
+    return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, 16>(p, stream);
 }
 
 #define V3(TS, TC, DT, SH, R, T) \
@@ -373,7 +362,7 @@ hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
 #define V3_S(TS, TC, DT)                                                                      \
     V3_T(TS, TC, DT, STENCIL_STAR, 1), V3_T(TS, TC, DT, STENCIL_STAR, 2),                     \
         V3(TS, TC, DT, STENCIL_STAR, 3, 1), V3(TS, TC, DT, STENCIL_STAR, 3, 2),               \
-        V3_T(TS, TC, DT, STENCIL_BOX, 1), V3(TS, TC, DT, STENCIL_BOX, 2, 1)
+        V3_T(TS, TC, DT, STENCIL_BOX, 1)
 
 }  // namespace
 
@@ -382,8 +371,6 @@ const std::vector<KernelEntry> &valu3d_kernels()
     static const std::vector<KernelEntry> table = {
         V3_S(double, double, STENCIL_F64),
         V3_S(float, float, STENCIL_F32),
-        // box r = 3 in float32 only (float64 would spill; it runs on the direct kernel)
-        V3(float, float, STENCIL_F32, STENCIL_BOX, 3, 1),
     };
     return table;
 }

@@ -77,12 +77,16 @@ class _Active:
 
 
 def choose_T(stl, job, candidates=(1, 2, 3, 4)) -> int:
-    """Fusion depth with the best model prediction for the plan's path
-    (VALU), never more than the job's steps."""
+    """Fusion depth with the best model prediction for the job's path (VALU
+    unless the job names one), among the depths the library fuses in one
+    pass, never more than the job's steps."""
+    path = job.path or "valu"
     best, best_gst = 1, -1.0
     for T in candidates:
         if T > max(1, job.steps):
             break
+        if T > 1 and not stl.kernel_available(path, job.dtype, job.shape, job.d, job.r, T):
+            continue
         m = stl.model_predict(job.shape, job.d, job.r, T, job.dtype)
         # a larger T also pays a skirt of r*T recomputed points per tile edge
         gst = m["gst_valu"] * (1.0 - 0.02 * job.r * T)

@@ -131,6 +131,19 @@ def test_valu3d(stl, shape, r, T, dt, boundary):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("r", [2, 3])
+def test_valu3d_large_box_many_tiles(stl, r, dt):
+    """Boxes with r >= 2 run on the one-step kernel: several in-plane tiles and
+    plane segments with ragged edges, Dirichlet halo h = 0.25, two steps."""
+    dims = (37, 70, 133)
+    u0, u0r, t, w = case_inputs("box", 3, r, dims, dt, seed=5200 + r)
+    p = stl.Plan("box", 3, r, w, dims, T=1, dtype=dt, path="valu", boundary="dirichlet", halo=0.25)
+    got = run_gpu(p, t, 2)
+    ref = oracle("box", 3, r, w, u0, 2, "dirichlet", 0.25)
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
 def test_config3_shapes_reduced(stl):
     """Star-3D2R and Box-3D1R, periodic, T = 3 with a remainder pass (50 steps
     at full size; 8 steps here on 64^3)."""
