@@ -18,10 +18,11 @@
 // The weights never occupy vector registers: each run of 2R+1 weights
 // w[c][a][-R..R] (one "block") is fetched with scalar loads from the
 // kernel-argument block just before its FMAs (v_fma takes it as the scalar
-// operand).  Empty volatile asm statements, which keep their relative order,
-// pin the schedule: the fetch of block n+1 is issued after the FMAs of block
-// n-1 have produced their results, so at most two blocks of weights are live
-// in scalar registers and each fetch overlaps the previous block's FMAs.
+// operand).  The fetch of block n+1 is issued before the FMAs of block n
+// (software pipelining), and empty volatile asm statements, which keep their
+// relative order, stop the compiler from hoisting fetches further: the fetch
+// of block n+2 waits for the results of block n-1, so at most three blocks of
+// weights are live in scalar registers.
 //
 // Contributions to one output arrive in canonical order (c, then a, then b
 // ascending), as in the oracle.
@@ -165,43 +166,52 @@ __global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
                 for (int e = 0; e < VE; ++e) row[v * VE + e] = t.e[e];
             }
         };
-        int m_prev = -1;       // accumulator plane of the previous block
+        // blocks n = 0 .. Q*Q-1 in order (a = n / Q, c = n % Q - R): the
+        // weights of block n+1 are fetched while block n runs
+        // Scalar loads complete out of order, so any wait for one waits for all:
+        // the fetch of block n+1 takes block n's first weight as an operand,
+        // which puts it after the wait for block n's weights (and it then runs
+        // under block n's FMAs).
+        auto fetch_w = [&](int n, TC *wv, TC after) {
+            int wrow = ((n % Q) * Q + n / Q) * Q;  // canonical index of w[c][a][-R]
+            asm volatile("" : "+s"(wrow) : "s"(after));  // W(n)
+#pragma unroll
+            for (int b = 0; b < Q; ++b) wv[b] = wk[wrow + b];
+        };
+        TC wcur[Q], wnxt[Q];
+        fetch_w(0, wcur, TC(0));
         TC rr[WY][WINV * VE];  // window rows a .. a+WY-1 (row a+i serves output row i)
 #pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            if (a == 0) {
+        for (int n = 0; n < Q * Q; ++n) {
+            const int a = n / Q, c = n % Q - R;
+            if (n == 0) {
 #pragma unroll
                 for (int i = 0; i < WY; ++i) load_row(rr[i], i);
-            } else {
+            } else if (c == -R) {
 #pragma unroll
                 for (int i = 0; i + 1 < WY; ++i)
 #pragma unroll
                     for (int e = 0; e < WINV * VE; ++e) rr[i][e] = rr[i + 1][e];
                 load_row(rr[WY - 1], a + WY - 1);
             }
-#pragma unroll
-            for (int c = -R; c <= R; ++c) {
-                const int m = R - c;  // accumulator plane of output z - c
-                // W(n): this block's weight fetch is issued after E(n-2)
-                int wrow = ((c + R) * Q + a) * Q;
-                asm volatile("" : "+s"(wrow));
-                TC wv[Q];
-#pragma unroll
-                for (int b = 0; b < Q; ++b) wv[b] = wk[wrow + b];
-                // E(n-1): the previous block's FMAs are done before W(n+1)
-                if (m_prev >= 0)
-#pragma unroll
-                    for (int i = 0; i < WY; ++i)
-#pragma unroll
-                        for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[m_prev][i][j]));
+            if (n + 1 < Q * Q) fetch_w(n + 1, wnxt, wcur[0]);
+            // E(n-1): block n-1 has produced its results before W(n+2)
+            if (n >= 1) {
+                const int mp = R - ((n - 1) % Q - R);
 #pragma unroll
                 for (int i = 0; i < WY; ++i)
 #pragma unroll
-                    for (int b = 0; b < Q; ++b)
-#pragma unroll
-                        for (int j = 0; j < W; ++j) acc[m][i][j] = fma_c(wv[b], rr[i][j + b], acc[m][i][j]);
-                m_prev = m;
+                    for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[mp][i][j]));
             }
+            const int m = R - c;  // accumulator plane of output z - c
+#pragma unroll
+            for (int i = 0; i < WY; ++i)
+#pragma unroll
+                for (int b = 0; b < Q; ++b)
+#pragma unroll
+                    for (int j = 0; j < W; ++j) acc[m][i][j] = fma_c(wcur[b], rr[i][j + b], acc[m][i][j]);
+#pragma unroll
+            for (int b = 0; b < Q; ++b) wcur[b] = wnxt[b];
         }
         // accumulator plane 0 is output plane zb + k - R
         const int zo = zb + k - R;
@@ -286,13 +296,17 @@ hipError_t launch_box3_cfg(const PassArgs &p, hipStream_t stream)
     return hipGetLastError();
 }
 
-// Tiles: 16 x 16 threads, WY = 2 rows each; float32 4 columns per thread
-// (32 x 64 outputs), float64 2 (32 x 32).
+// Tiles: 16 columns of threads with one 16-byte vector each (float32 4
+// points, float64 2) and one row per thread; 16 thread rows for r = 3, 32 for
+// r = 2.  Measured on 384^3 / 512^3 periodic grids against 2-row threads,
+// 3-row threads and 8 x 32 / 32 x 8 thread tiles: the one-row threads need
+// 70-96 VGPRs and keep 5-7 waves per SIMD, which hides the LDS and
+// scalar-load latencies best (5-15 % faster).
 template <typename TS, typename TC, int R>
 hipError_t launch_box3(const PassArgs &p, hipStream_t stream)
 {
     constexpr int W = sizeof(TC) == 8 ? 2 : 4;
-    return launch_box3_cfg<TS, TC, R, W, 2, 16, 16>(p, stream);
+    return launch_box3_cfg<TS, TC, R, W, 1, 16, (R >= 3 ? 16 : 32)>(p, stream);
 }
 
 #define B3(TS, TC, DT, R) {STENCIL_PATH_VALU, DT, STENCIL_BOX, 3, R, 1, &launch_box3<TS, TC, R>, nullptr}
