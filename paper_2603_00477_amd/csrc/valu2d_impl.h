@@ -30,6 +30,8 @@
 
 #pragma once
 
+#include <cstddef>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -68,7 +70,31 @@ struct Valu2DCfg {
     static constexpr int Q = 2 * R + 1;
     // rows prefetched ahead: a multiple of Q, at least 4
     static constexpr int U = Q * ((4 + Q - 1) / Q);
+    // Boxes whose weights exceed 48 dwords (float64 r >= 2, float32 r = 3)
+    // fused over T >= 3 steps keep them out of the vector registers: stored
+    // column-major (w[b][a]), each column of 2R+1 is scalar-loaded just before
+    // its FMAs.  That frees 49-98 VGPRs for the T stages' accumulators
+    // (Box-2D3R float64 T = 4: 232 instead of 340 registers, no spills, +30 %
+    // measured); at T <= 2 the weights pinned in VGPRs measured as fast or
+    // faster (float32 T = 2: 632 vs 478 GSt/s), so they stay there.
+    static constexpr bool WPTR = SHAPE == STENCIL_BOX && sizeof(TC) * K > 192 && T >= 3;
 };
+
+// Weights in constant memory (scalar loads).
+template <typename TC>
+using ConstPtr = const __attribute__((address_space(4))) TC *;
+
+// Weight order the kernels expect: canonical, or column-major for WPTR boxes.
+template <typename Cfg, int R>
+__host__ __device__ constexpr int weight_slot(int k)
+{
+    if constexpr (Cfg::WPTR) {
+        const int a = k / (2 * R + 1), b = k % (2 * R + 1);
+        return b * (2 * R + 1) + a;
+    } else {
+        return k;
+    }
+}
 
 template <int SHAPE, int R>
 __device__ __forceinline__ int star_axis_index(int axis, int off)
@@ -113,8 +139,10 @@ __device__ __forceinline__ void assemble_window(const TC (&own)[W], TC (&win)[W 
 // One tile (column band x row segment) of one pass, run by one wave.
 template <typename TS, typename TC, int SHAPE, int R, int T, int W>
 __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
-                                            const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W>::K],
-                                            int band, int seg, int lane)
+                                            const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W>::WPTR
+                                                               ? 1
+                                                               : Valu2DCfg<TS, TC, SHAPE, R, T, W>::K],
+                                            ConstPtr<TC> wp, int band, int seg, int lane)
 {
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, W>;
     constexpr int Q = Cfg::Q;
@@ -189,6 +217,22 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
     for (int u = 0; u < U; ++u)
         if (u < KTOT) load_row(u, ring[u]);
 
+    // WPTR: weight column b (2R+1 values) of the block being computed and of
+    // the next one.  Scalar loads complete out of order, so any wait for one
+    // waits for all: the fetch of the next column takes the current column's
+    // first weight as an operand, which puts it after the wait for the
+    // current column (it then runs under the current block's FMAs).  Empty
+    // volatile asm statements on the previous block's accumulators keep the
+    // compiler from hoisting fetches further ahead.
+    TC wcur[Q], wnxt[Q];
+    auto fetch_col = [&](int b, TC *dstw, TC after) {
+        int off = b * Q;
+        asm volatile("" : "+s"(off) : "s"(after));
+#pragma unroll
+        for (int e = 0; e < Q; ++e) dstw[e] = wp[off + e];
+    };
+    if constexpr (Cfg::WPTR) fetch_col(0, wcur, TC(0));
+
     for (int kb = 0; kb < KTOT; kb += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -207,26 +251,47 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                 for (int j = 0; j < W; ++j) outv[j] = TC(0);
                 if (active) {
                     const TC *win = wins[s - 1];
+                    if constexpr (Cfg::WPTR) {
 #pragma unroll
-                    for (int bo = -R; bo <= R; ++bo) {
+                        for (int bo = -R; bo <= R; ++bo) {
+                            fetch_col(bo + R < 2 * R ? bo + R + 1 : 0, wnxt, wcur[0]);
+                            if (bo > -R)  // previous column's FMAs done before the fetch after next
 #pragma unroll
-                        for (int ao = -R; ao <= R; ++ao) {
-                            const int q = ((u - ao + R) % Q + Q) % Q;
-                            if (SHAPE == STENCIL_BOX) {
-                                const TC wv = wk[(ao + R) * (2 * R + 1) + (bo + R)];
+                                for (int q = 0; q < Q; ++q)
 #pragma unroll
-                                for (int j = 0; j < W; ++j)
-                                    acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
-                            } else if (ao != 0 && bo == 0) {
-                                const TC wv = wk[star_axis_index<SHAPE, R>(0, ao)];
+                                    for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[s - 1][q][j]));
 #pragma unroll
-                                for (int j = 0; j < W; ++j)
-                                    acc[s - 1][q][j] = fma_c(wv, win[j + R], acc[s - 1][q][j]);
-                            } else if (ao == 0) {
-                                const TC wv = bo == 0 ? wk[0] : wk[star_axis_index<SHAPE, R>(1, bo)];
+                            for (int ao = -R; ao <= R; ++ao) {
+                                const int q = ((u - ao + R) % Q + Q) % Q;
 #pragma unroll
                                 for (int j = 0; j < W; ++j)
-                                    acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
+                                    acc[s - 1][q][j] = fma_c(wcur[ao + R], win[j + bo + R], acc[s - 1][q][j]);
+                            }
+#pragma unroll
+                            for (int e = 0; e < Q; ++e) wcur[e] = wnxt[e];
+                        }
+                    } else {
+#pragma unroll
+                        for (int bo = -R; bo <= R; ++bo) {
+#pragma unroll
+                            for (int ao = -R; ao <= R; ++ao) {
+                                const int q = ((u - ao + R) % Q + Q) % Q;
+                                if constexpr (SHAPE == STENCIL_BOX) {
+                                    const TC wv = wk[(ao + R) * (2 * R + 1) + (bo + R)];
+#pragma unroll
+                                    for (int j = 0; j < W; ++j)
+                                        acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
+                                } else if (ao != 0 && bo == 0) {
+                                    const TC wv = wk[star_axis_index<SHAPE, R>(0, ao)];
+#pragma unroll
+                                    for (int j = 0; j < W; ++j)
+                                        acc[s - 1][q][j] = fma_c(wv, win[j + R], acc[s - 1][q][j]);
+                                } else if (ao == 0) {
+                                    const TC wv = bo == 0 ? wk[0] : wk[star_axis_index<SHAPE, R>(1, bo)];
+#pragma unroll
+                                    for (int j = 0; j < W; ++j)
+                                        acc[s - 1][q][j] = fma_c(wv, win[j + bo + R], acc[s - 1][q][j]);
+                                }
                             }
                         }
                     }
@@ -301,9 +366,19 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_kernel(
     if (g >= a.g.nwg) return;
     const int band = (g / a.g.nsegs) * kValu2DWaves + (int)(threadIdx.x >> 6);
     if (band >= a.g.nbands) return;
-    TC wk[Cfg::K];
-    load_weights(wk, a.w);
-    valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, band, g % a.g.nsegs, threadIdx.x & 63);
+    TC wk[Cfg::WPTR ? 1 : Cfg::K];
+    ConstPtr<TC> wp = nullptr;
+    if constexpr (Cfg::WPTR) {
+        // the argument block is the first entry of the kernel-argument segment
+        using Args = Valu2DArgs<TC, Cfg::K>;
+        wp = (ConstPtr<TC>)((const __attribute__((address_space(4))) char *)
+                                __builtin_amdgcn_kernarg_segment_ptr() +
+                            offsetof(Args, w));
+        wk[0] = TC(0);
+    } else {
+        load_weights(wk, a.w);
+    }
+    valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, wp, band, g % a.g.nsegs, threadIdx.x & 63);
 }
 
 // One job of a batched launch: geometry plus weights.
@@ -332,9 +407,15 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
         const int local = item - tile_start[j];
         const int band = (local / g.nsegs) * kValu2DWaves + wave;
         if (band >= g.nbands) continue;
-        TC wk[Cfg::K];
-        load_weights(wk, jobs[j].w);
-        valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, band, local % g.nsegs, lane);
+        TC wk[Cfg::WPTR ? 1 : Cfg::K];
+        ConstPtr<TC> wp = nullptr;
+        if constexpr (Cfg::WPTR) {
+            wp = (ConstPtr<TC>)(jobs[j].w);  // the job table is read-only in the kernel
+            wk[0] = TC(0);
+        } else {
+            load_weights(wk, jobs[j].w);
+        }
+        valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, wp, band, local % g.nsegs, lane);
     }
 }
 
@@ -408,7 +489,7 @@ hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
     PassArgs q = p;
     q.slots_per_cu = occ;
     if (!valu2d_geometry<TS, TC, SHAPE, R, T>(q, &a.g, &err)) return err;
-    for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
+    for (int k = 0; k < Cfg::K; ++k) a.w[weight_slot<Cfg, R>(k)] = (TC)p.w[k];
     const int grid = a.g.nwg;
     hipLaunchKernelGGL((valu2d_kernel<TS, TC, SHAPE, R, T, S::W>), dim3(grid), dim3(64 * kValu2DWaves), 0,
                        stream, a);
@@ -432,7 +513,7 @@ hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
             if (err != hipSuccess) return err;
             continue;
         }
-        for (int k = 0; k < Cfg::K; ++k) j.w[k] = (TC)ps[i].w[k];
+        for (int k = 0; k < Cfg::K; ++k) j.w[weight_slot<Cfg, R>(k)] = (TC)ps[i].w[k];
         jobs.push_back(j);
         start.push_back(start.back() + j.g.nwg);
     }

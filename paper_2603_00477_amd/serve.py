@@ -96,9 +96,16 @@ def choose_T(stl, job, candidates=(1, 2, 3, 4)) -> int:
 
 
 class GpuExecutor:
-    """Device work of the server, through the HIP library."""
+    """Device work of the server, through the HIP library.
 
-    def __init__(self, device="cuda", stream=None):
+    Jobs are spread over `streams` HIP streams (default priority): 2D jobs
+    share stream 0, where the passes of one kernel variant go out as one
+    batched launch; 3D jobs, which have no batched kernel, rotate over the
+    other streams so that their launches can overlap on the device when they
+    are too small to fill it.  A job stays on its stream, so its passes run in
+    order."""
+
+    def __init__(self, device="cuda", stream=None, streams=4):
         import torch
 
         import paper_2603_00477_amd as stl
@@ -106,7 +113,10 @@ class GpuExecutor:
         self.torch = torch
         self.stl = stl
         self.device = torch.device(device)
-        self.stream = stream or torch.cuda.Stream(device=self.device)
+        first = stream or torch.cuda.Stream(device=self.device)
+        self.streams = [first] + [torch.cuda.Stream(device=self.device) for _ in range(max(0, streams - 1))]
+        self.stream = first
+        self._rr = 0
         self._plans = {}
 
     def _plan(self, job):
@@ -120,11 +130,18 @@ class GpuExecutor:
         D = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}[job.dtype]
         return 2 * int(np.prod(job.dims)) * D + (1 << 20)
 
+    def _stream_index(self, job) -> int:
+        if job.d == 2 or len(self.streams) == 1:
+            return 0
+        self._rr += 1
+        return 1 + self._rr % (len(self.streams) - 1)
+
     def prepare(self, job):
         torch = self.torch
         plan = self._plan(job)
         tdt = self.stl.torch_dtype(job.dtype)
-        with torch.cuda.stream(self.stream):
+        si = self._stream_index(job)
+        with torch.cuda.stream(self.streams[si]):
             if callable(job.data):
                 a = job.data(self.device)
             elif isinstance(job.data, torch.Tensor):
@@ -133,29 +150,46 @@ class GpuExecutor:
                 a = torch.as_tensor(np.asarray(job.data)).to(self.device)
             a = a.to(tdt).contiguous()
             b = torch.empty_like(a)
-        return {"plan": plan, "a": a, "b": b, "T": plan.info()["T"]}
+        return {"plan": plan, "a": a, "b": b, "T": plan.info()["T"], "stream": si}
 
     def run_round(self, states, steps):
-        """One pass of every state; returns an event that fires when done."""
+        """One pass of every state (one batched call per stream used);
+        returns the events that fire when the passes are done."""
         torch = self.torch
-        plans = [s["plan"] for s in states]
-        ins = [s["a"] for s in states]
-        outs = [s["b"] for s in states]
-        self.stl.run_batch(plans, ins, outs, steps, stream=self.stream)
-        for s in states:
-            s["a"], s["b"] = s["b"], s["a"]
-        ev = torch.cuda.Event()
-        ev.record(self.stream)
-        return ev
+        by = {}
+        for s, k in zip(states, steps):
+            by.setdefault(s["stream"], []).append((s, k))
+        for s in states:  # argument checks before any launch
+            s["plan"]._check_tensor(s["a"], "in")
+            s["plan"]._check_tensor(s["b"], "out")
+        events, launched = [], []
+        for si, items in sorted(by.items()):
+            st = [s for s, _ in items]
+            try:
+                self.stl.run_batch([s["plan"] for s in st], [s["a"] for s in st], [s["b"] for s in st],
+                                   [k for _, k in items], stream=self.streams[si])
+            except Exception as e:
+                # passes of earlier groups are queued: report them so that
+                # the caller does not run them a second time
+                e.launched, e.handle = launched, events
+                raise
+            for s in st:
+                s["a"], s["b"] = s["b"], s["a"]
+            launched.extend(st)
+            ev = torch.cuda.Event()
+            ev.record(self.streams[si])
+            events.append(ev)
+        return events
 
     def pass_steps(self, state, left) -> int:
         return min(state["T"], left)
 
     def done(self, handle) -> bool:
-        return handle.query()
+        return all(e.query() for e in handle)
 
     def wait(self, handle):
-        handle.synchronize()
+        for e in handle:
+            e.synchronize()
 
     def result(self, state):
         return state["a"]
@@ -163,6 +197,11 @@ class GpuExecutor:
     def release(self, state):
         state["plan"].close()
         state["b"] = None
+
+
+class _Joined(list):
+    """Several executor handles of one round (a round that had to be split);
+    the round is complete when every part is."""
 
 
 class StencilServer:
@@ -210,6 +249,13 @@ class StencilServer:
             self._thread.join()
 
     # ---- scheduler
+    def _h_done(self, h) -> bool:
+        return all(self.ex.done(x) for x in h) if isinstance(h, _Joined) else self.ex.done(h)
+
+    def _h_wait(self, h):
+        for x in (h if isinstance(h, _Joined) else [h]):
+            self.ex.wait(x)
+
     def _admit(self):
         while self._queue:
             job, fut, arrival = self._queue[0]
@@ -249,7 +295,7 @@ class StencilServer:
     def _reap_ready(self):
         """Finish the jobs of every completed round at the head of the queue
         (never waits; called with the lock held)."""
-        while self._inflight and self.ex.done(self._inflight[0][0]):
+        while self._inflight and self._h_done(self._inflight[0][0]):
             _, fin = self._inflight.popleft()
             now = self.clock()
             for a in fin:
@@ -276,26 +322,34 @@ class StencilServer:
                 if not runnable or len(self._inflight) >= self.max_inflight:
                     wait_on = self._inflight[0][0]
             if wait_on is not None:
-                self.ex.wait(wait_on)  # outside the lock: clients can submit/stop meanwhile
+                self._h_wait(wait_on)  # outside the lock: clients can submit/stop meanwhile
                 continue
             steps = [self.ex.pass_steps(a.state, a.left) for a in runnable]
             try:
                 h = self.ex.run_round([a.state for a in runnable], steps)
-            except Exception:
+            except Exception as exc:
                 # isolate: run each job's pass alone; only jobs that fail
-                # again are failed, the others keep their pass
-                ok, ok_steps, h = [], [], None
+                # again are failed, the others keep their pass.  Passes the
+                # executor reports as already queued are not run again.
+                queued = getattr(exc, "launched", None) or []
+                ok, ok_steps = [], []
+                hs = list(getattr(exc, "handle", None) or [])
                 for a, s in zip(runnable, steps):
+                    if any(a.state is q for q in queued):
+                        ok.append(a)
+                        ok_steps.append(s)
+                        continue
                     try:
-                        h = self.ex.run_round([a.state], [s])
+                        hs.append(self.ex.run_round([a.state], [s]))
                         ok.append(a)
                         ok_steps.append(s)
                     except Exception as e:
                         with self._cv:
                             self._fail(a, e)
                 runnable, steps = ok, ok_steps
-                if h is None:
+                if not hs:
                     continue
+                h = _Joined(hs) if len(hs) > 1 else hs[0]
             self.rounds += 1
             with self._cv:
                 fin = []

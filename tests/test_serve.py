@@ -126,6 +126,34 @@ def test_invalid_and_failing_jobs_isolated():
     assert srv.used == 0
 
 
+class PartialExecutor(FakeExecutor):
+    """A round whose later part fails after its first job's pass was queued
+    (as a multi-stream executor reports it)."""
+
+    def run_round(self, states, steps):
+        ids = [s["job"].id for s in states]
+        if self.fail_round_with in ids and len(states) > 1:
+            first = states[0]
+            h = FakeExecutor.run_round(self, [first], steps[:1])
+            e = RuntimeError("device error in a later group")
+            e.launched, e.handle = [first], [h]
+            raise e
+        return FakeExecutor.run_round(self, states, steps)
+
+
+def test_partially_launched_round_is_not_run_twice():
+    ex = PartialExecutor(pass_time=0.002, T=1, fail_round_with="r")
+    srv = StencilServer(ex, hbm_budget=1000)
+    ok = srv.submit(_job("ok", steps=4))
+    r = srv.submit(_job("r", steps=3))
+    srv.start()
+    assert ok.result(timeout=10).output == ("out", "ok", 4)  # exactly one pass per step
+    with pytest.raises(RuntimeError):
+        r.result(timeout=10)
+    srv.stop()
+    assert srv.used == 0
+
+
 def test_continuous_batching_late_arrivals_join_running_rounds():
     ex = FakeExecutor(pass_time=0.002, T=1)
     srv = StencilServer(ex, hbm_budget=1000).start()
