@@ -8,19 +8,21 @@ Headline (one "step" = one whole sweep of the workload through the library):
   paths.  The JSON line's value is Box-2D3R float64 at the fastest (path, T).
 
 Further sections (extra keys of the same JSON line):
-  model_check  config 3 (Star-3D2R, Box-3D1R, 512^3, periodic, 50 steps,
-               T in {1,2,3}) plus the config-2 variants: the model's
+  model_check  the 3D workload (Star-3D2R, Box-3D1R, 512^3, periodic, 50
+               steps, T in {1,2,3}) plus the 8192^2 variants: the model's
                predicted winner (VALU / tie / MFMA, tie band 0.87-1.15) next
                to the measured one.
-  precision    config 4 (Box-2D2R, 16384^2, periodic, 1000 steps, smooth
-               sin(2 pi x) sin(2 pi y) + 1e-3 U[0,1) data): bf16 / f16 MFMA with
+  precision    Box-2D2R, 16384^2, periodic, 1000 steps, smooth
+               sin(2 pi x) sin(2 pi y) + 1e-3 U[0,1) data: bf16 / f16 MFMA with
                float32 accumulation, compensated bf16x3, VALU comparators;
                relative max-norm error against the float64 GPU sweep every 100
                steps, and GStencil/s.
-  serving      config 5 (4096 jobs, Poisson arrivals, mixed shape/d/r/size/
-               steps, float32, HBM budget): continuous-batching server vs
+  serving      served stream (4096 jobs, Poisson arrivals, mixed shape/d/r/
+               size/steps, float32, HBM budget): continuous-batching server vs
                one-plan-per-call FIFO on the same trace; p50/p99 latency and
                aggregate GStencil/s.
+  paper_cases  the six cases of the paper's Table 3 at 10240^2 / 1024^3 on
+               both paths, predicted vs measured winner.
 
 GStencil/s = grid points x time steps / seconds / 1e9 (grids resident in HBM
 before the timed region).  Kernel time comes from HIP events recorded on the
@@ -73,7 +75,7 @@ def parse():
     ap.add_argument("--time-steps", type=int, default=100, help="stencil steps per sweep")
     ap.add_argument("--n", type=int, default=8192, help="grid side of the headline workload")
     ap.add_argument("--only", default="", help="comma list of headline variant names to run")
-    ap.add_argument("--sections", default="c2,c3,c4,c5")
+    ap.add_argument("--sections", default="c2,c3,c4,c5,cases")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jobs", type=int, default=4096, help="served-stream jobs")
@@ -150,7 +152,7 @@ def verdict(ratio):
     return "mfma" if ratio > 1.15 else ("valu" if ratio < 0.87 else "tie")
 
 
-# ---------------------------------------------------------------- config 2
+# ---------------------------------------------------------------- 8192^2 2D workload
 def headline_variants(n, nsteps):
     out = []
     for shape, K in (("box", 49), ("star", 13)):
@@ -194,7 +196,7 @@ def section_c2(stl, args):
     return results
 
 
-# ---------------------------------------------------------------- config 3
+# ---------------------------------------------------------------- 512^3 3D workload
 def section_c3(stl, args):
     import torch
 
@@ -241,7 +243,67 @@ def model_check(c2, c3):
     return dict(cases=rows, agree=agree, total=len(rows))
 
 
-# ---------------------------------------------------------------- config 4
+# ---------------------------------------------------------------- paper's cases
+# The six representative cases of the paper's Table 3 (pattern, fusion depth,
+# type), run on MI355X at the paper's domain sizes (10240^2, 1024^3; Sec.
+# "Experiments"): both paths at that depth, the model's predicted winner next
+# to the measured one.  The A100 GStencil/s the paper prints (CUDA-core
+# baseline, Tensor-Core implementation) are quoted as context only.
+PAPER_CASES = [
+    ("1", "box", 2, 1, 3, "f64", (260.90, 190.14)),
+    ("2", "box", 2, 3, 1, "f64", (64.05, 63.33)),
+    ("3", "box", 2, 1, 7, "f32", (318.31, 1002.94)),
+    ("4", "box", 2, 7, 1, "f32", (50.35, 143.28)),
+    ("5", "box", 3, 1, 3, "f64", (37.74, 24.63)),
+    ("6", "box", 3, 1, 7, "f32", (71.23, 51.13)),
+]
+
+
+def section_cases(stl, args):
+    import torch
+
+    import stencil_inputs as si
+
+    out = {}
+    for case, shape, d, r, T, dt, a100 in PAPER_CASES:
+        n = 10240 if d == 2 else 1024
+        dims = (n,) * d
+        K = (2 * r + 1) ** d
+        w = si.normalised_weights(K, seed=si.weight_seed(6, int(case)))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(si.data_seed(6, int(case)))
+        x = torch.rand(dims, generator=g, device="cuda", dtype=torch.float64).to(stl.torch_dtype(dt))
+        row = dict(pattern=f"{shape}-{d}d{r}r", T=T, dtype=dt, dims=list(dims), a100_gst=list(a100))
+        m = stl.model_predict(shape, d, r, T, dt)
+        row["predicted"] = {-1: "valu", 0: "tie", 1: "mfma"}[m["winner"]]
+        row["predicted_ratio"] = m["ratio"]
+        row["scenario"] = m["scenario"]
+        for path in ("valu", "mfma"):
+            Tp = T
+            if not stl.kernel_available(path, dt, shape, d, r, T):
+                if path == "mfma":
+                    row[path] = dict(error=f"no MFMA kernel with composite radius {r * T} in {d}D")
+                    continue
+                # deepest fused VALU depth this pattern has
+                Tp = max(t for t in range(1, T + 1) if stl.kernel_available(path, dt, shape, d, r, t))
+            v = dict(shape=shape, K=K, d=d, r=r, dtype=dt, T=Tp, path=path, dims=dims, steps=4 * Tp,
+                     boundary="periodic")
+            res = measure(stl, v, x, w, 3, 1)
+            res["T_run"] = Tp
+            row[path] = res
+        if "gst" in row["valu"] and "gst" in row.get("mfma", {}):
+            row["measured"] = verdict(row["mfma"]["gst"] / row["valu"]["gst"])
+            row["measured_ratio"] = row["mfma"]["gst"] / row["valu"]["gst"]
+        out[case] = row
+        log(f"case {case} {row['pattern']} T{T} {dt}: valu {row['valu'].get('gst', float('nan')):.1f} "
+            f"(T={row['valu'].get('T_run')}), mfma {row.get('mfma', {}).get('gst', float('nan')):.1f}; "
+            f"predicted {row['predicted']}, measured {row.get('measured', '-')}")
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------- 16384^2 precision workload
 def section_c4(stl, args):
     import numpy as np
     import torch
@@ -301,7 +363,7 @@ def section_c4(stl, args):
     return out
 
 
-# ---------------------------------------------------------------- config 5
+# ---------------------------------------------------------------- served stream
 def _served_jobs(stl, trace, scale_arrivals=1.0):
     import torch
 
@@ -459,6 +521,7 @@ def main():
     c3 = section_c3(stl, args) if "c3" in sections else {}
     c4 = section_c4(stl, args) if "c4" in sections else None
     c5 = section_serving(stl, args) if "c5" in sections else None
+    cases = section_cases(stl, args) if "cases" in sections else None
     cpu = None if args.no_cpu or not head_name else cpu_baseline(args.n, args.cpu_seconds)
     head = ok.get(head_name, {})
     hv = next((v for v in headline_variants(args.n, args.time_steps) if v["name"] == head_name), None)
@@ -491,6 +554,7 @@ def main():
         "model_check": model_check(c2, c3) if (c2 or c3) else None,
         "precision": c4,
         "serving": c5,
+        "paper_cases": cases,
     }
     s = json.dumps(line)
     print(s, flush=True)

@@ -76,8 +76,9 @@ struct Valu2DCfg {
     // its FMAs.  That frees 49-98 VGPRs for the T stages' accumulators
     // (Box-2D3R float64 T = 4: 232 instead of 340 registers, no spills, +30 %
     // measured); at T <= 2 the weights pinned in VGPRs measured as fast or
-    // faster (float32 T = 2: 632 vs 478 GSt/s), so they stay there.
-    static constexpr bool WPTR = SHAPE == STENCIL_BOX && sizeof(TC) * K > 192 && T >= 3;
+    // faster (float32 T = 2: 632 vs 478 GSt/s), so they stay there unless
+    // they need more than 128 dwords (r = 7: 225 weights).
+    static constexpr bool WPTR = SHAPE == STENCIL_BOX && sizeof(TC) * K > 192 && (T >= 3 || sizeof(TC) * K > 512);
 };
 
 // Weights in constant memory (scalar loads).

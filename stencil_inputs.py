@@ -42,12 +42,12 @@ def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(int(seed)))
 
 
-def data_seed(config: int, variant: int = 0) -> int:
-    return 1000 * int(config) + int(variant)
+def data_seed(workload: int, variant: int = 0) -> int:
+    return 1000 * int(workload) + int(variant)
 
 
-def weight_seed(config: int, variant: int = 0) -> int:
-    return 1000 * int(config) + 500 + int(variant)
+def weight_seed(workload: int, variant: int = 0) -> int:
+    return 1000 * int(workload) + 500 + int(variant)
 
 
 def uniform_grid(dims, seed: int) -> np.ndarray:

@@ -25,7 +25,7 @@ def stl():
     return stl
 
 
-def test_config1_star2d1r_jacobi(stl):
+def test_star2d1r_jacobi_512(stl):
     """Star-2D1R, weights 0.2, 512x512 FP64, U[0,1) seed 1001, zero Dirichlet
     halo, 10 steps, T = 1."""
     u0 = si.uniform_grid((512, 512), seed=si.data_seed(1, 1))
@@ -59,6 +59,25 @@ def test_valu2d_periodic(stl, shape, r, T, dt):
     p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, boundary="periodic", path="valu")
     got = run_gpu(p, t, steps)
     ref = oracle(shape, 2, r, w, u0, steps, "periodic")
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
+# the paper's evaluation patterns: r = 1 fused 5..8 deep, r = 7
+CASES_EVAL = ([(shape, 1, T, dt) for shape in ("star", "box") for T in (5, 6, 7, 8) for dt in ("f64", "f32")]
+              + [("box", 7, 1, "f64"), ("box", 7, 1, "f32"), ("star", 7, 1, "f32"), ("star", 7, 1, "f64")])
+
+
+@pytest.mark.parametrize("shape,r,T,dt", CASES_EVAL)
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+def test_valu2d_eval_patterns(stl, shape, r, T, dt, boundary):
+    """Deep fusion and radius 7 over several column bands and row segments
+    with ragged edges; steps = T + 3 adds a remainder pass."""
+    dims = (203, 1000)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=2600 + 10 * r + T)
+    steps = T + 3
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="valu", boundary=boundary, halo=0.25)
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0, steps, boundary, 0.25)
     assert rel_inf(got, ref) <= TOL[dt]
 
 
@@ -144,7 +163,7 @@ def test_valu3d_large_box_many_tiles(stl, r, dt):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
-def test_config3_shapes_reduced(stl):
+def test_3d_periodic_patterns_reduced(stl):
     """Star-3D2R and Box-3D1R, periodic, T = 3 with a remainder pass (50 steps
     at full size; 8 steps here on 64^3)."""
     for shape, r in (("star", 2), ("box", 1)):
