@@ -2,7 +2,7 @@
 
 Two commands:
 
-  python -m paper_2603_00477_amd.counters run [--n2 N] [--n3 N]
+  python -m paper_2603_00477_amd.counters run [--n2 N] [--n3 N] [--set model|ai_t]
       Runs one pass (T fused steps) of each listed variant on the GPU, two
       times, so that a rocprofv3 counter pass records every kernel.  Prints a
       JSON line per variant with the grid size and the model's C, M, I.
@@ -36,18 +36,24 @@ VARIANTS_2D = [(s, 3, T, dt, path) for s in ("box", "star") for dt in ("f64", "f
 VARIANTS_3D = [(s, r, T, dt, path) for s, r in (("star", 2), ("box", 1)) for dt in ("f64", "f32")
                for T in (1, 2, 3) for path in ("valu", "mfma")]
 VARIANTS_16 = [("box", 2, T, dt, "mfma") for dt in ("bf16", "f16", "bf16x3") for T in (1, 2, 4)]
+# arithmetic intensity against fusion depth on the vector units (paper,
+# Sec. "Arithmetic Intensity Analysis": Box-2D1R and Star-2D1R, double)
+VARIANTS_AI_T = [(s, 1, T, "f64", "valu") for s in ("box", "star") for T in range(1, 9)]
 
 
 def _k(shape, d, r):
     return (2 * r + 1) ** d if shape == "box" else 2 * d * r + 1
 
 
-def run(n2: int, n3: int):
+def run(n2: int, n3: int, which: str = "model"):
     import torch
 
     import paper_2603_00477_amd as stl
 
-    todo = [(2, v) for v in VARIANTS_2D] + [(3, v) for v in VARIANTS_3D] + [(2, v) for v in VARIANTS_16]
+    if which == "ai_t":
+        todo = [(2, v) for v in VARIANTS_AI_T]
+    else:
+        todo = [(2, v) for v in VARIANTS_2D] + [(3, v) for v in VARIANTS_3D] + [(2, v) for v in VARIANTS_16]
     x_cache = {}
     for d, (shape, r, T, dt, path) in todo:
         dims = (n2, n2) if d == 2 else (n3, n3, n3)
@@ -145,6 +151,9 @@ def main(argv=None):
     r = sub.add_parser("run")
     r.add_argument("--n2", type=int, default=4096)
     r.add_argument("--n3", type=int, default=256)
+    r.add_argument("--set", default="model", choices=["model", "ai_t"],
+                   help="model: every 8192^2 / 512^3 / precision variant; ai_t: Box/Star-2D1R "
+                        "float64 at T = 1..8")
     rep = sub.add_parser("report")
     rep.add_argument("fetch")
     rep.add_argument("write")
@@ -155,7 +164,7 @@ def main(argv=None):
     rep.add_argument("--f-write", type=float, default=1.0)
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run(a.n2, a.n3)
+        run(a.n2, a.n3, a.set)
     else:
         report(a.fetch, a.write, a.sq, a.runs, a.f_fetch, a.f_write)
 
