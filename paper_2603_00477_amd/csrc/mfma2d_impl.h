@@ -187,9 +187,13 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
         if (row < LRD) {
             int gr = r0 - R + row, gc = c0 - R + col;
             const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
-            if (in || periodic) {
-                gr = wrap(gr, n0);
-                gc = wrap(gc, n1);
+            // points past n + R only feed outputs of a partial tile that are
+            // not stored; the rest lie in [-R, n + R), where one fold wraps
+            // (periodic plans have every dim >= 2R + 1)
+            const bool used = gr < n0 + R && gc < n1 + R;
+            if (in || (periodic && used)) {
+                gr = wrap1(gr, n0);
+                gc = wrap1(gc, n1);
                 const auto v = load_val(src[(int64_t)gr * n1 + gc]);
                 vf = (float)v;
                 vd = (double)v;

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(64 * NW) void mfma3d_kernel(Mfma3DArgs a)
     // this thread's staging slots: element e = tid + i*NT of the LRD x LC block
     auto fetch = [&](int z, SV (&v)[PT]) {
         const bool zin = z >= 0 && z < n0;
-        const int zz = periodic ? wrap(z, n0) : z;
+        const int zz = periodic ? wrap1(z, n0) : z;  // every dim >= 2R + 1: one fold suffices
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
             const int e = tid + i * NT;
@@ -95,9 +95,12 @@ __global__ __launch_bounds__(64 * NW) void mfma3d_kernel(Mfma3DArgs a)
             const int row = e / LC, col = e - (e / LC) * LC;
             int gy = y0 - R + row, gx = x0 - R + col;
             const bool in = zin && gy >= 0 && gy < n1 && gx >= 0 && gx < n2;
-            if (in || periodic) {
-                gy = wrap(gy, n1);
-                gx = wrap(gx, n2);
+            // points past n + R feed only unstored outputs of partial tiles;
+            // the rest lie in [-R, n + R), where one fold wraps
+            const bool used = gy < n1 + R && gx < n2 + R;
+            if (in || (periodic && used)) {
+                gy = wrap1(gy, n1);
+                gx = wrap1(gx, n2);
                 v[i] = load_val(src[((int64_t)zz * n1 + gy) * n2 + gx]);
             }
         }

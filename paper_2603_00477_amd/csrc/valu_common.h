@@ -29,6 +29,9 @@ __device__ __forceinline__ int wrap(int i, int n)
     return m < 0 ? m + n : m;
 }
 
+// wrap for -n <= i < 2n (a halo no wider than the grid): no division
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 __device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 

@@ -65,6 +65,20 @@ def test_mfma2d_radius7_composites(stl, r, T, dt, boundary):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
+@pytest.mark.parametrize("shape,r,T,dims", [("box", 1, 4, (17, 23)), ("star", 2, 2, (9, 70)),
+                                            ("box", 7, 1, (15, 40)), ("box", 1, 7, (15, 15))])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_mfma2d_small_periodic(stl, shape, r, T, dims, dt):
+    """Periodic grids smaller than one 64 x 64 tile, down to the minimum
+    2rT + 1 points per axis: the staged block wraps more than once."""
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6700 + 10 * r + T)
+    steps = 2 * T
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma", boundary="periodic")
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0, steps, "periodic")
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
 def test_mfma_matches_valu_f64(stl):
     dims = (257, 300)
     u0, u0r, t, w = case_inputs("box", 2, 3, dims, "f64", seed=6100)
@@ -126,3 +140,13 @@ def test_mfma3d(stl, shape, r, T, dt, boundary):
     got = run_gpu(p, t, steps)
     ref = oracle(shape, 3, r, w, u0, steps, boundary, 0.25)
     assert rel_inf(got, ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("shape,r,T,dims", [("box", 1, 3, (9, 11, 13)), ("star", 2, 2, (9, 20, 70))])
+def test_mfma3d_small_periodic(stl, shape, r, T, dims):
+    """Periodic 3D grids smaller than one in-plane tile."""
+    u0, u0r, t, w = case_inputs(shape, 3, r, dims, "f64", seed=6800 + 10 * r + T)
+    p = stl.Plan(shape, 3, r, w, dims, T=T, dtype="f64", path="mfma", boundary="periodic")
+    got = run_gpu(p, t, 2 * T)
+    ref = oracle(shape, 3, r, w, u0, 2 * T, "periodic")
+    assert rel_inf(got, ref) <= 1e-12
