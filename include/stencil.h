@@ -91,7 +91,7 @@ typedef struct {
     double S;          /* sparsity factor of the MFMA operand layout          */
     double gamma;      /* products per useful MAC (3 for bf16x3, else 1)      */
     double halo;       /* Dirichlet halo value                                */
-    int64_t workspace_bytes; /* device memory the plan owns                   */
+    int64_t workspace_bytes; /* device memory the plan may own (upper bound) */
     double predicted_gst_valu;  /* model, GStencil/s                          */
     double predicted_gst_mfma;
     int predicted_winner;       /* -1 VALU, 0 tie, +1 MFMA                    */
@@ -104,8 +104,11 @@ typedef struct {
  * return), dims[d] (each >= 1; periodic needs every dim >= 2*r*T + 1 on the
  * MFMA path), fusion depth T >= 1, storage dtype and boundary.
  * The plan owns a scratch grid for ping-pong passes and the MFMA operand
- * blocks (size in workspace_bytes).  Path AUTO resolves to the model's
- * predicted winner among the paths built for this combination.
+ * blocks (upper bound in workspace_bytes).  Device memory is allocated on the
+ * device current at the first run: the operand blocks then, the scratch grid
+ * only when a run needs two or more passes (a run of steps <= T needs none).
+ * Path AUTO resolves to the model's predicted winner among the paths built
+ * for this combination.
  * Errors: INVALID_ARG (d not in {2,3}, r < 1, T < 1, NULL or non-finite
  * weights, dims < 1), UNSUPPORTED, OOM, HIP.  On error *plan is NULL.
  */

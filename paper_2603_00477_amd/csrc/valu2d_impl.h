@@ -10,7 +10,7 @@
 //   and no barrier: neighbour columns come from cross-lane permutes.
 //
 // Step pipeline
-//   Stage 0 takes input row k (prefetched U rows ahead into registers).
+//   Stage 0 takes input row k (prefetched P rows ahead into registers).
 //   Stage s = 1..T consumes the row stage s-1 produced one iteration earlier,
 //   as a (W + 2R)-column window assembled by permutes at the end of that
 //   iteration (so the permute latency overlaps the next row's arithmetic).
@@ -70,6 +70,10 @@ struct Valu2DCfg {
     static constexpr int Q = 2 * R + 1;
     // rows prefetched ahead: a multiple of Q, at least 4
     static constexpr int U = Q * ((4 + Q - 1) / Q);
+    // input rows in flight: U for small Q; for r = 7 (Q = 15, compute-bound,
+    // 225 or 29 FMAs per input value) 3 rows, a divisor of U, so the ring
+    // slot of row k is k mod P at compile time and 48 VGPRs stay free
+    static constexpr int P = U <= 8 ? U : (U % 3 == 0 ? 3 : (U % 4 == 0 ? 4 : (U % 5 == 0 ? 5 : U)));
     // Boxes whose weights exceed 48 dwords (float64 r >= 2, float32 r = 3)
     // fused over T >= 3 steps keep them out of the vector registers: stored
     // column-major (w[b][a]), each column of 2R+1 is scalar-loaded just before
@@ -213,18 +217,20 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
         }
     };
 
-    Vec ring[U];
+    constexpr int P = Cfg::P;
+    Vec ring[P];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < P; ++u)
         if (u < KTOT) load_row(u, ring[u]);
 
     // WPTR: weight column b (2R+1 values) of the block being computed and of
     // the next one.  Scalar loads complete out of order, so any wait for one
     // waits for all: the fetch of the next column takes the current column's
     // first weight as an operand, which puts it after the wait for the
-    // current column (it then runs under the current block's FMAs).  Empty
-    // volatile asm statements on the previous block's accumulators keep the
-    // compiler from hoisting fetches further ahead.
+    // current column, and an empty volatile asm statement on the current
+    // block's accumulators after its FMAs keeps the next wait behind them
+    // (volatile asm statements keep their order), so each fetch overlaps a
+    // whole block of FMAs and at most two columns are live.
     TC wcur[Q], wnxt[Q];
     auto fetch_col = [&](int b, TC *dstw, TC after) {
         int off = b * Q;
@@ -256,11 +262,6 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
 #pragma unroll
                         for (int bo = -R; bo <= R; ++bo) {
                             fetch_col(bo + R < 2 * R ? bo + R + 1 : 0, wnxt, wcur[0]);
-                            if (bo > -R)  // previous column's FMAs done before the fetch after next
-#pragma unroll
-                                for (int q = 0; q < Q; ++q)
-#pragma unroll
-                                    for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[s - 1][q][j]));
 #pragma unroll
                             for (int ao = -R; ao <= R; ++ao) {
                                 const int q = ((u - ao + R) % Q + Q) % Q;
@@ -268,6 +269,13 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                                 for (int j = 0; j < W; ++j)
                                     acc[s - 1][q][j] = fma_c(wcur[ao + R], win[j + bo + R], acc[s - 1][q][j]);
                             }
+                            // this column's FMAs complete before the wait for the
+                            // next column's weights (which the fetch after next
+                            // needs), so that fetch runs under all of them
+#pragma unroll
+                            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                                for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[s - 1][q][j]));
 #pragma unroll
                             for (int e = 0; e < Q; ++e) wcur[e] = wnxt[e];
                         }
@@ -329,12 +337,12 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                 // window of this stage's row for stage s+1 at the next iteration
                 if (s < T) assemble_window<TC, W, R>(outv, wins[s], lane);
             }
-            // ---- stage 0: input row (window for stage 1), prefetch U rows ahead
+            // ---- stage 0: input row (window for stage 1), prefetch P rows ahead
             {
                 TC inrow[W];
 #pragma unroll
-                for (int j = 0; j < W; ++j) inrow[j] = to_compute<TC>(ring[u].e[j]);
-                if (k + U < KTOT) load_row(k + U, ring[u]);
+                for (int j = 0; j < W; ++j) inrow[j] = to_compute<TC>(ring[u % P].e[j]);
+                if (k + P < KTOT) load_row(k + P, ring[u % P]);
                 assemble_window<TC, W, R>(inrow, wins[0], lane);
             }
         }

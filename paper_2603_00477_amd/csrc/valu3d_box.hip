@@ -19,10 +19,12 @@
 // w[c][a][-R..R] (one "block") is fetched with scalar loads from the
 // kernel-argument block just before its FMAs (v_fma takes it as the scalar
 // operand).  The fetch of block n+1 is issued before the FMAs of block n
-// (software pipelining), and empty volatile asm statements, which keep their
-// relative order, stop the compiler from hoisting fetches further: the fetch
-// of block n+2 waits for the results of block n-1, so at most three blocks of
-// weights are live in scalar registers.
+// (software pipelining).  Scalar loads complete out of order, so a wait for
+// one waits for all; empty volatile asm statements, which keep their relative
+// order, pin the waits: the fetch of block n+1 takes block n's first weight
+// as an operand (it follows the wait for block n), and a statement consuming
+// block n's results follows its FMAs, so the wait for block n+1 comes after
+// them and at most two blocks of weights are live in scalar registers.
 //
 // Contributions to one output arrive in canonical order (c, then a, then b
 // ascending), as in the oracle.
@@ -195,14 +197,6 @@ __global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
                 load_row(rr[WY - 1], a + WY - 1);
             }
             if (n + 1 < Q * Q) fetch_w(n + 1, wnxt, wcur[0]);
-            // E(n-1): block n-1 has produced its results before W(n+2)
-            if (n >= 1) {
-                const int mp = R - ((n - 1) % Q - R);
-#pragma unroll
-                for (int i = 0; i < WY; ++i)
-#pragma unroll
-                    for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[mp][i][j]));
-            }
             const int m = R - c;  // accumulator plane of output z - c
 #pragma unroll
             for (int i = 0; i < WY; ++i)
@@ -210,6 +204,12 @@ __global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
                 for (int b = 0; b < Q; ++b)
 #pragma unroll
                     for (int j = 0; j < W; ++j) acc[m][i][j] = fma_c(wcur[b], rr[i][j + b], acc[m][i][j]);
+            // E(n): block n's results exist before W(n+2), whose operand
+            // needs block n+1's weights: the wait for them follows block n
+#pragma unroll
+            for (int i = 0; i < WY; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[m][i][j]));
 #pragma unroll
             for (int b = 0; b < Q; ++b) wcur[b] = wnxt[b];
         }
