@@ -179,40 +179,54 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
     const bool periodic = a.periodic != 0;
     const TS *src = static_cast<const TS *>(a.src);
 
-    // ---- stage the input block (boundary rule applied) in LDS
-    for (int idx = tid; idx < LR * LC; idx += NT) {
-        const int row = idx / LC, col = idx - (idx / LC) * LC;
-        float vf = 0.f;
-        double vd = 0.0;
-        if (row < LRD) {
-            int gr = r0 - R + row, gc = c0 - R + col;
-            const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
-            // points past n + R only feed outputs of a partial tile that are
-            // not stored; the rest lie in [-R, n + R), where one fold wraps
-            // (periodic plans have every dim >= 2R + 1)
-            const bool used = gr < n0 + R && gc < n1 + R;
-            if (in || (periodic && used)) {
-                gr = wrap1(gr, n0);
-                gc = wrap1(gc, n1);
-                const auto v = load_val(src[(int64_t)gr * n1 + gc]);
-                vf = (float)v;
-                vd = (double)v;
+    // ---- stage the input block (boundary rule applied) in LDS.  A thread's
+    // loads are issued in batches of CH before the batch's LDS writes (one
+    // wait per batch rather than one memory latency per element): the whole
+    // block for 32/64-bit data; 8 elements for 16-bit data, whose kernels
+    // need the occupancy more than the fewer waits.
+    constexpr int NE = (LR * LC + NT - 1) / NT;  // elements per thread
+    constexpr int CH = sizeof(TS) == 2 ? (NE < 8 ? NE : 8) : NE;
+    using SV = decltype(load_val(TS{}));
+#pragma unroll
+    for (int c0e = 0; c0e < NE; c0e += CH) {
+        SV vals[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int idx = tid + (c0e + i) * NT;
+            const int row = idx / LC, col = idx - (idx / LC) * LC;
+            vals[i] = SV(a.h);
+            if (c0e + i < NE && idx < LR * LC && row < LRD) {
+                int gr = r0 - R + row, gc = c0 - R + col;
+                const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
+                // points past n + R only feed outputs of a partial tile that
+                // are not stored; the rest lie in [-R, n + R), where one fold
+                // wraps (periodic plans have every dim >= 2R + 1)
+                const bool used = gr < n0 + R && gc < n1 + R;
+                if (in || (periodic && used)) {
+                    gr = wrap1(gr, n0);
+                    gc = wrap1(gc, n1);
+                    vals[i] = load_val(src[(int64_t)gr * n1 + gc]);
+                }
             } else {
-                vf = (float)a.h;
-                vd = a.h;
+                vals[i] = SV(0);  // rows past the data rows: zeros for the last k-blocks
             }
         }
-        const int li = KDIM == 4 ? row * LCP + col : col * LR + row;
-        if constexpr (sizeof(OP) == 8) {
-            lhi[li] = vd;
-        } else if constexpr (sizeof(OP) == 4) {
-            lhi[li] = vf;
-        } else if constexpr (X3) {
-            const OP hi = (OP)vf;
-            lhi[li] = hi;
-            llo[li] = (OP)(vf - (float)hi);
-        } else {
-            lhi[li] = (OP)vf;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int idx = tid + (c0e + i) * NT;
+            if (c0e + i >= NE || idx >= LR * LC) break;
+            const int row = idx / LC, col = idx - (idx / LC) * LC;
+            const int li = KDIM == 4 ? row * LCP + col : col * LR + row;
+            if constexpr (sizeof(OP) == 8 || sizeof(OP) == 4) {
+                lhi[li] = (OP)vals[i];
+            } else if constexpr (X3) {
+                const float vf = (float)vals[i];
+                const OP hi = (OP)vf;
+                lhi[li] = hi;
+                llo[li] = (OP)(vf - (float)hi);
+            } else {
+                lhi[li] = (OP)(float)vals[i];
+            }
         }
     }
     __syncthreads();
