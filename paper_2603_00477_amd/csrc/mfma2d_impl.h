@@ -153,6 +153,36 @@ struct Mfma2DCfg {
     static constexpr int LDS_ELEMS = KDIM == 4 ? LR * LCP : LC * LR;
 };
 
+// Non-empty kernel columns of the composite, in order, and the depth of the
+// A-fragment prefetch of the float64/float32 kernels: operand fragments of
+// the next PF columns are in flight while a column's MFMAs run, within a
+// register budget of 64 VGPRs.  The 16-bit kernels load a column's fragments
+// at the column (measured faster: they need the occupancy more).
+template <int SHAPE, int r, int T, int KDIM, int FRW>
+struct BandCols {
+    static constexpr int R = r * T;
+    static constexpr int count()
+    {
+        int n = 0;
+        for (int b = -R; b <= R; ++b) n += band_amax(SHAPE, r, T, 0, b) >= 0;
+        return n;
+    }
+    static constexpr int col(int j)
+    {
+        int n = 0;
+        for (int b = -R; b <= R; ++b)
+            if (band_amax(SHAPE, r, T, 0, b) >= 0) {
+                if (n == j) return b;
+                ++n;
+            }
+        return 0;
+    }
+    static constexpr int N = count();
+    static constexpr int NB = band_nblk(SHAPE, r, T, 0, 0, KDIM);  // k-blocks of the widest column
+    static constexpr int PF0 = 64 / (NB * FRW);
+    static constexpr int PF = PF0 < 2 ? 2 : (PF0 > N ? N : PF0);
+};
+
 template <int DT, int SHAPE, int r, int T, int V, int NW>
 __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 {
@@ -178,6 +208,29 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
     const int n0 = a.n0, n1 = a.n1;
     const bool periodic = a.periodic != 0;
     const TS *src = static_cast<const TS *>(a.src);
+
+    // ---- A fragments of the first PF columns: in flight during the staging
+    const int lane = tid & 63, wave = tid >> 6;
+    const FR *afr = static_cast<const FR *>(a.afrag);
+    const FR *afr_lo = static_cast<const FR *>(a.afrag_lo);
+    using Cols = BandCols<SHAPE, r, T, KDIM, (sizeof(FR) + 3) / 4 * (X3 ? 2 : 1)>;
+    constexpr int NBMAX = Cols::NB, PF = KDIM == 4 ? Cols::PF : 1;
+    FR Ar[PF][NBMAX], Alr[X3 ? PF : 1][X3 ? NBMAX : 1];
+    auto load_col = [&](int j, int slot) {
+        const int b = Cols::col(j);
+        const int klo = band_kk_lo(SHAPE, r, T, 0, b, KDIM);
+        const int khi = band_kk_hi(SHAPE, r, T, 0, b, KDIM);
+        const int off = band_frag_offset(SHAPE, r, T, 0, b, KDIM, 2);
+#pragma unroll
+        for (int i = 0; i < NBMAX; ++i)
+            if (i <= khi - klo) {
+                Ar[slot][i] = afr[(off + i) * 64 + lane];
+                if constexpr (X3) Alr[slot][i] = afr_lo[(off + i) * 64 + lane];
+            }
+    };
+    if constexpr (KDIM == 4)
+#pragma unroll
+        for (int j = 0; j < PF; ++j) load_col(j, j);
 
     // ---- stage the input block (boundary rule applied) in LDS.  A thread's
     // loads are issued in batches of CH before the batch's LDS writes (one
@@ -231,31 +284,20 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
     }
     __syncthreads();
 
-    const int lane = tid & 63, wave = tid >> 6;
     const int lg = lane >> 4, ln = lane & 15;
     const int wc0 = 16 * wave;
     ACC acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = ACC{};
 
-    const FR *afr = static_cast<const FR *>(a.afrag);
-    const FR *afr_lo = static_cast<const FR *>(a.afrag_lo);
-
 #pragma unroll
-    for (int b = -R; b <= R; ++b) {
-        const int amax = band_amax(SHAPE, r, T, 0, b);
-        if (amax < 0) continue;
+    for (int j = 0; j < Cols::N; ++j) {
+        const int b = Cols::col(j);
         const int klo = band_kk_lo(SHAPE, r, T, 0, b, KDIM);
         const int khi = band_kk_hi(SHAPE, r, T, 0, b, KDIM);
-        const int off = band_frag_offset(SHAPE, r, T, 0, b, KDIM, 2);
-        constexpr int NBMAX = band_nblk(SHAPE, r, T, 0, 0, KDIM);
-        FR A[NBMAX], Alo[X3 ? NBMAX : 1];
-#pragma unroll
-        for (int i = 0; i < NBMAX; ++i)
-            if (i <= khi - klo) {
-                A[i] = afr[(off + i) * 64 + lane];
-                if constexpr (X3) Alo[i] = afr_lo[(off + i) * 64 + lane];
-            }
+        const int slot = j % PF;
+        if constexpr (KDIM != 4) load_col(j, 0);
+        const FR(&A)[NBMAX] = Ar[slot];
         const int col = wc0 + ln + b + R;
         if constexpr (KDIM == 4) {
 #pragma unroll
@@ -281,10 +323,12 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
                     if constexpr (X3) {
                         const FR Bl = *reinterpret_cast<const FR *>(&llo[col * LR + row]);
                         acc[v] = mfma16(A[i], Bl, acc[v]);
-                        acc[v] = mfma16(Alo[i], B, acc[v]);
+                        acc[v] = mfma16(Alr[slot][i], B, acc[v]);
                     }
                 }
         }
+        if constexpr (KDIM == 4)
+            if (j + PF < Cols::N) load_col(j + PF, slot);  // refill the slot just used
     }
 
     // ---- store the stacked tiles (output register layout per instruction)
