@@ -18,6 +18,8 @@
 // accumulated in float32.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -147,7 +149,11 @@ struct Mfma2DCfg {
     static constexpr int KKH = band_kk_hi(SHAPE, r, T, 0, 0, KDIM);
     static constexpr int LRK = 16 * (V - 1) + KDIM * (KKH + 1);  // rows an operand may touch
     static constexpr int LR0 = LRD > LRK ? LRD : LRK;
-    static constexpr int LR = ((LR0 + 7) / 8) * 8;
+    // column-major blocks (16-bit operands): an odd number of 16-byte units
+    // per column, so the 16 columns one B-fragment read touches fall in
+    // distinct bank groups
+    static constexpr int LR8 = ((LR0 + 7) / 8) * 8;
+    static constexpr int LR = LR8 + (KDIM != 4 && (LR8 / 8) % 2 == 0 ? 8 : 0);
     // row-major pitch (KDIM = 4) padded off multiples of the bank count
     static constexpr int LCP = LC + ((LC % 32) == 0 ? 1 : 0);
     static constexpr int LDS_ELEMS = KDIM == 4 ? LR * LCP : LC * LR;
@@ -232,53 +238,123 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 #pragma unroll
         for (int j = 0; j < PF; ++j) load_col(j, j);
 
-    // ---- stage the input block (boundary rule applied) in LDS.  A thread's
-    // loads are issued in batches of CH before the batch's LDS writes (one
-    // wait per batch rather than one memory latency per element): the whole
-    // block for 32/64-bit data; 8 elements for 16-bit data, whose kernels
-    // need the occupancy more than the fewer waits.
-    constexpr int NE = (LR * LC + NT - 1) / NT;  // elements per thread
-    constexpr int CH = sizeof(TS) == 2 ? (NE < 8 ? NE : 8) : NE;
-    using SV = decltype(load_val(TS{}));
+    // ---- 16-bit operands (bf16/f16 storage, or float storage split into
+    // bf16 hi/lo), interior tile: rows are read in aligned chunks of four
+    // elements (one 8- or 16-byte load each) and scattered into the
+    // column-major block; one wait per batch of chunks.
+    bool staged = false;
+    if constexpr (KDIM != 4) {
+        using Chunk = typename std::conditional<sizeof(TS) == 2, uint2, uint4>::type;
+        constexpr int NCH = (LC + 3 + 3) / 4;  // chunks per row (start aligned down by up to 3)
+        constexpr int NE4 = (LRD * NCH + NT - 1) / NT;
+        constexpr int CB = NE4 < 8 ? NE4 : 8;
+        const int cs = (c0 - R) & ~3;
+        const int lead = (c0 - R) - cs;
+        const bool fast = r0 - R >= 0 && r0 - R + LRD <= n0 && c0 - R >= 0 && cs + 4 * NCH <= n1 &&
+                          (n1 % 4) == 0 && (reinterpret_cast<uintptr_t>(src) % sizeof(Chunk)) == 0;
+        if (fast) {
+            uint16_t *l16 = reinterpret_cast<uint16_t *>(lhi);
+            uint16_t *l16lo = reinterpret_cast<uint16_t *>(llo);
 #pragma unroll
-    for (int c0e = 0; c0e < NE; c0e += CH) {
-        SV vals[CH];
+            for (int e0 = 0; e0 < NE4; e0 += CB) {
+                Chunk v[CB];
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int idx = tid + (c0e + i) * NT;
-            const int row = idx / LC, col = idx - (idx / LC) * LC;
-            vals[i] = SV(a.h);
-            if (c0e + i < NE && idx < LR * LC && row < LRD) {
-                int gr = r0 - R + row, gc = c0 - R + col;
-                const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
-                // points past n + R only feed outputs of a partial tile that
-                // are not stored; the rest lie in [-R, n + R), where one fold
-                // wraps (periodic plans have every dim >= 2R + 1)
-                const bool used = gr < n0 + R && gc < n1 + R;
-                if (in || (periodic && used)) {
-                    gr = wrap1(gr, n0);
-                    gc = wrap1(gc, n1);
-                    vals[i] = load_val(src[(int64_t)gr * n1 + gc]);
+                for (int i = 0; i < CB; ++i) {
+                    const int e = tid + (e0 + i) * NT;
+                    const int row = e / NCH, ch = e - (e / NCH) * NCH;
+                    if (e0 + i < NE4 && e < LRD * NCH)
+                        v[i] = *reinterpret_cast<const Chunk *>(src + (int64_t)(r0 - R + row) * n1 + cs + 4 * ch);
                 }
-            } else {
-                vals[i] = SV(0);  // rows past the data rows: zeros for the last k-blocks
-            }
-        }
 #pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int idx = tid + (c0e + i) * NT;
-            if (c0e + i >= NE || idx >= LR * LC) break;
-            const int row = idx / LC, col = idx - (idx / LC) * LC;
-            const int li = KDIM == 4 ? row * LCP + col : col * LR + row;
-            if constexpr (sizeof(OP) == 8 || sizeof(OP) == 4) {
-                lhi[li] = (OP)vals[i];
-            } else if constexpr (X3) {
-                const float vf = (float)vals[i];
-                const OP hi = (OP)vf;
-                lhi[li] = hi;
-                llo[li] = (OP)(vf - (float)hi);
-            } else {
-                lhi[li] = (OP)(float)vals[i];
+                for (int i = 0; i < CB; ++i) {
+                    const int e = tid + (e0 + i) * NT;
+                    if (e0 + i >= NE4 || e >= LRD * NCH) break;
+                    const int row = e / NCH, ch = e - (e / NCH) * NCH;
+                    uint16_t hi4[4], lo4[4];
+                    if constexpr (sizeof(TS) == 2) {
+                        hi4[0] = (uint16_t)(v[i].x & 0xffff);
+                        hi4[1] = (uint16_t)(v[i].x >> 16);
+                        hi4[2] = (uint16_t)(v[i].y & 0xffff);
+                        hi4[3] = (uint16_t)(v[i].y >> 16);
+                    } else {  // compensated: x = hi + lo in bf16, hi rounded to nearest even
+                        const uint32_t u[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float f = __uint_as_float(u[j]);
+                            const OP h = (OP)f;
+                            const OP l = (OP)(f - (float)h);
+                            hi4[j] = __builtin_bit_cast(uint16_t, h);
+                            lo4[j] = __builtin_bit_cast(uint16_t, l);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int col = 4 * ch + j - lead;
+                        if (col >= 0 && col < LC) {
+                            l16[col * LR + row] = hi4[j];
+                            if constexpr (X3) l16lo[col * LR + row] = lo4[j];
+                        }
+                    }
+                }
+            }
+            // rows past the data rows: zeros for the last k-blocks
+            for (int e = tid; e < (LR - LRD) * LC; e += NT) {
+                const int row = LRD + e / LC, col = e - (e / LC) * LC;
+                l16[col * LR + row] = 0;
+                if constexpr (X3) l16lo[col * LR + row] = 0;
+            }
+            staged = true;
+        }
+    }
+    if (!staged) {
+        // ---- stage the input block (boundary rule applied) in LDS.  A thread's
+        // loads are issued in batches of CH before the batch's LDS writes (one
+        // wait per batch rather than one memory latency per element): the whole
+        // block for 32/64-bit data; 8 elements for 16-bit data, whose kernels
+        // need the occupancy more than the fewer waits.
+        constexpr int NE = (LR * LC + NT - 1) / NT;  // elements per thread
+        constexpr int CH = sizeof(TS) == 2 ? (NE < 8 ? NE : 8) : NE;
+        using SV = decltype(load_val(TS{}));
+#pragma unroll
+        for (int c0e = 0; c0e < NE; c0e += CH) {
+            SV vals[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int idx = tid + (c0e + i) * NT;
+                const int row = idx / LC, col = idx - (idx / LC) * LC;
+                vals[i] = SV(a.h);
+                if (c0e + i < NE && idx < LR * LC && row < LRD) {
+                    int gr = r0 - R + row, gc = c0 - R + col;
+                    const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
+                    // points past n + R only feed outputs of a partial tile that
+                    // are not stored; the rest lie in [-R, n + R), where one fold
+                    // wraps (periodic plans have every dim >= 2R + 1)
+                    const bool used = gr < n0 + R && gc < n1 + R;
+                    if (in || (periodic && used)) {
+                        gr = wrap1(gr, n0);
+                        gc = wrap1(gc, n1);
+                        vals[i] = load_val(src[(int64_t)gr * n1 + gc]);
+                    }
+                } else {
+                    vals[i] = SV(0);  // rows past the data rows: zeros for the last k-blocks
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int idx = tid + (c0e + i) * NT;
+                if (c0e + i >= NE || idx >= LR * LC) break;
+                const int row = idx / LC, col = idx - (idx / LC) * LC;
+                const int li = KDIM == 4 ? row * LCP + col : col * LR + row;
+                if constexpr (sizeof(OP) == 8 || sizeof(OP) == 4) {
+                    lhi[li] = (OP)vals[i];
+                } else if constexpr (X3) {
+                    const float vf = (float)vals[i];
+                    const OP hi = (OP)vf;
+                    lhi[li] = hi;
+                    llo[li] = (OP)(vf - (float)hi);
+                } else {
+                    lhi[li] = (OP)(float)vals[i];
+                }
             }
         }
     }
