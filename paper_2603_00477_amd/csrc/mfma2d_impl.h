@@ -306,6 +306,48 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
             staged = true;
         }
     }
+    // ---- float64/float32 operands, interior tile: rows are read in aligned
+    // 16-byte chunks (2 or 4 elements) and written to the row-major block.
+    if constexpr (KDIM == 4) {
+        constexpr int EPC = 16 / (int)sizeof(TS);       // elements per chunk
+        constexpr int NCH = (LC + 2 * (EPC - 1)) / EPC;  // chunks per row (start aligned down)
+        constexpr int NE4 = (LRD * NCH + NT - 1) / NT;
+        constexpr int CB = NE4 < 8 ? NE4 : 8;
+        const int cs = (c0 - R) & ~(EPC - 1);
+        const int lead = (c0 - R) - cs;
+        const bool fast = r0 - R >= 0 && r0 - R + LRD <= n0 && c0 - R >= 0 && cs + EPC * NCH <= n1 &&
+                          (n1 % EPC) == 0 && (reinterpret_cast<uintptr_t>(src) % 16) == 0;
+        if (fast) {
+#pragma unroll
+            for (int e0 = 0; e0 < NE4; e0 += CB) {
+                RawVec<TS, EPC> v[CB];
+#pragma unroll
+                for (int i = 0; i < CB; ++i) {
+                    const int e = tid + (e0 + i) * NT;
+                    const int row = e / NCH, ch = e - (e / NCH) * NCH;
+                    if (e0 + i < NE4 && e < LRD * NCH)
+                        v[i].load(src + (int64_t)(r0 - R + row) * n1 + cs + EPC * ch);
+                }
+#pragma unroll
+                for (int i = 0; i < CB; ++i) {
+                    const int e = tid + (e0 + i) * NT;
+                    if (e0 + i >= NE4 || e >= LRD * NCH) break;
+                    const int row = e / NCH, ch = e - (e / NCH) * NCH;
+#pragma unroll
+                    for (int j = 0; j < EPC; ++j) {
+                        const int col = EPC * ch + j - lead;
+                        if (col >= 0 && col < LC) lhi[row * LCP + col] = (OP)v[i].e[j];
+                    }
+                }
+            }
+            // rows past the data rows: zeros for the last k-blocks
+            for (int e = tid; e < (LR - LRD) * LC; e += NT) {
+                const int row = LRD + e / LC, col = e - (e / LC) * LC;
+                lhi[row * LCP + col] = OP(0);
+            }
+            staged = true;
+        }
+    }
     if (!staged) {
         // ---- stage the input block (boundary rule applied) in LDS.  A thread's
         // loads are issued in batches of CH before the batch's LDS writes (one
