@@ -355,9 +355,14 @@ hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
     // passes keep 16 x 16 (faster there by 10-40 %)
     if constexpr (T == 1) {
         return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, 2, 32, 8>(p, stream);
+    } else if constexpr (R * T >= 6) {
+        // deep composite halos: 4 rows per thread spilled to AGPRs; measured on
+        // 512^3, Star-3D2R T = 3 runs best with 1 row x 32 thread rows (+26-36 %),
+        // Star-3D3R T = 2 with 2 rows x 16 (+25 %)
+        constexpr int WY = R >= 3 ? 2 : 1;
+        return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, 32 / WY>(p, stream);
     } else {
-        constexpr int WY = (R * T >= 6) ? 4 : 2;
-        return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, 16>(p, stream);
+        return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, 2, 16, 16>(p, stream);
     }
 }
 
