@@ -234,9 +234,14 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
     TC wcur[Q], wnxt[Q];
     auto fetch_col = [&](int b, TC *dstw, TC after) {
         int off = b * Q;
-        asm volatile("" : "+s"(off) : "s"(after));
+        if constexpr (sizeof(TC) == 4) asm volatile("" : "+s"(off) : "v"(after));
+        else asm volatile("" : "+s"(off) : "s"(after));
 #pragma unroll
-        for (int e = 0; e < Q; ++e) dstw[e] = wp[off + e];
+        for (int e = 0; e < Q; ++e) {
+            dstw[e] = wp[off + e];
+            // float32: FMAs run faster on vector-register operands (one move each)
+            if constexpr (sizeof(TC) == 4) asm volatile("" : "+v"(dstw[e]));
+        }
     };
     if constexpr (Cfg::WPTR) fetch_col(0, wcur, TC(0));
 
@@ -349,8 +354,11 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
     }
 }
 
-// Load the weights.  Scalar registers hold up to ~48 dwords; larger sets
-// (49 float64 box weights) are pinned in vector registers, otherwise the
+// Load the weights.  Float32 weights go to vector registers: a v_fma_f32 with a
+// scalar-register operand measured ~35 % slower on gfx950 than with vector
+// operands only (61-68 vs 92-97 TFLOP/s in FMA chains; float64 shows no such
+// difference).  Float64 sets up to ~48 dwords stay in scalar registers; larger
+// ones (49 float64 box weights) are pinned in vector registers, otherwise the
 // compiler spills them to vector lanes and pays a readlane per use.
 template <typename TC, int K, typename SrcT>
 __device__ __forceinline__ void load_weights(TC (&wk)[K], const SrcT *w)
@@ -358,7 +366,7 @@ __device__ __forceinline__ void load_weights(TC (&wk)[K], const SrcT *w)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         wk[k] = w[k];
-        if constexpr (sizeof(TC) * K > 192) asm volatile("" : "+v"(wk[k]));
+        if constexpr (sizeof(TC) == 4 || sizeof(TC) * K > 192) asm volatile("" : "+v"(wk[k]));
     }
 }
 

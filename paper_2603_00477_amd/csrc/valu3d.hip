@@ -52,7 +52,11 @@ struct Valu3DCfg {
     static constexpr int PLANE = LROWS * LDX;
     static constexpr int Q = 2 * R + 1;
     static constexpr int U = Q;                             // planes prefetched ahead
-    static constexpr int WMODE = sizeof(TC) * K <= 192 ? 0 : 1;
+    // 0: scalar registers; 1: pinned vector registers.  Float32 FMAs run ~35 %
+    // slower with a scalar-register operand on gfx950, so float32 sets go to
+    // vector registers for r <= 2 (+8-13 % measured); at r = 3 the extra
+    // registers cost more occupancy than they gain (-17 %), so they stay scalar
+    static constexpr int WMODE = (sizeof(TC) * K <= 192 && (sizeof(TC) == 8 || R >= 3)) ? 0 : 1;
     static_assert(sizeof(TC) * K <= 256, "large boxes run on the one-step box kernel");
 };
 
@@ -350,10 +354,10 @@ template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
 {
     constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
-    // one step per pass: 32 x 8 threads (wide rows: 64 float64 / 128 float32
-    // columns per tile), measured 14-18 % faster than 16 x 16 on 512^3; fused
-    // passes keep 16 x 16 (faster there by 10-40 %)
-    if constexpr (T == 1) {
+    // one step per pass, r <= 2: 32 x 8 threads (wide rows: 64 float64 / 128
+    // float32 columns per tile), measured 14-18 % faster than 16 x 16 on 512^3;
+    // r = 3 (Star-3D3R float32: 371 vs 294 GSt/s) and fused passes keep 16 x 16
+    if constexpr (T == 1 && R <= 2) {
         return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, 2, 32, 8>(p, stream);
     } else if constexpr (R * T >= 6) {
         // deep composite halos: 4 rows per thread spilled to AGPRs; measured on

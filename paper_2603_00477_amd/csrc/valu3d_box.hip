@@ -176,9 +176,16 @@ __global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
         // under block n's FMAs).
         auto fetch_w = [&](int n, TC *wv, TC after) {
             int wrow = ((n % Q) * Q + n / Q) * Q;  // canonical index of w[c][a][-R]
-            asm volatile("" : "+s"(wrow) : "s"(after));  // W(n)
+            if constexpr (sizeof(TC) == 4 && R == 2) asm volatile("" : "+s"(wrow) : "v"(after));  // W(n)
+            else asm volatile("" : "+s"(wrow) : "s"(after));
 #pragma unroll
-            for (int b = 0; b < Q; ++b) wv[b] = wk[wrow + b];
+            for (int b = 0; b < Q; ++b) {
+                wv[b] = wk[wrow + b];
+                // float32 r = 2: FMAs run faster on vector-register operands (one
+                // move each, +15 %); r = 3 keeps them scalar (the moves' registers
+                // cost a wave of occupancy, -9 %)
+                if constexpr (sizeof(TC) == 4 && R == 2) asm volatile("" : "+v"(wv[b]));
+            }
         };
         TC wcur[Q], wnxt[Q];
         fetch_w(0, wcur, TC(0));
