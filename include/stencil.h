@@ -236,7 +236,9 @@ int stencil_model_predict(const stencil_model_in_t *in, const stencil_hw_t *hw,
  *           a multiple of 32: first half copied to the second half)
  *   kind 1: FP64 vector FMA, kind 2: FP32 scalar vector FMA (flop/s)
  *   kind 3: MFMA f64 16x16x4, kind 4: MFMA f32 16x16x4,
- *   kind 5: MFMA bf16 16x16x32 (flop/s); `buf` unused for kinds 1-5.
+ *   kind 5: MFMA bf16 16x16x32 (flop/s);
+ *   kind 6: FP32 FMA with a scalar-register multiplier, kind 7: FP32 FMA with
+ *           vector-register operands only (flop/s); `buf` unused for kinds 1-7.
  * Errors: INVALID_ARG, OOM, HIP.
  */
 int stencil_microbench(int kind, void *buf, int64_t bytes, void *stream, double *result);

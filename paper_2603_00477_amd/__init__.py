@@ -164,10 +164,11 @@ def model_predict(shape, d, r, T, dtype, S=0.0, alpha=0.0, sparse=False, hw=None
 
 def microbench(kind: str, nbytes: int = 1 << 30) -> float:
     """Measured ceiling: 'copy' (bytes/s), 'fma_f64', 'fma_f32', 'mfma_f64',
-    'mfma_f32', 'mfma_bf16' (flop/s)."""
+    'mfma_f32', 'mfma_bf16', 'fma_f32_sgpr' / 'fma_f32_vgpr' (FP32 FMAs with a
+    scalar-register multiplier / vector operands only) (flop/s)."""
     import torch
 
-    kinds = ["copy", "fma_f64", "fma_f32", "mfma_f64", "mfma_f32", "mfma_bf16"]
+    kinds = ["copy", "fma_f64", "fma_f32", "mfma_f64", "mfma_f32", "mfma_bf16", "fma_f32_sgpr", "fma_f32_vgpr"]
     k = kinds.index(kind)
     buf = torch.empty(nbytes if k == 0 else 32, dtype=torch.uint8, device="cuda")
     out = ctypes.c_double()

@@ -38,6 +38,29 @@ __global__ __launch_bounds__(256) void mb_fma(F *out, int iters, F seed)
     if (s == (F)-1) out[threadIdx.x] = s;  // keeps the chains live
 }
 
+// FP32 FMA chains whose multiplier is a scalar register (SGPR = 1) or a
+// vector register (SGPR = 0), as the stencil kernels' weights are.
+template <int SGPR>
+__global__ __launch_bounds__(256) void mb_fma32_operand(float *out, int iters, const float *w)
+{
+    float x[16], y[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        x[c] = (float)(threadIdx.x + c) * 1e-3f;
+        y[c] = (float)((threadIdx.x & 7) + c + 1) * 0.5f;
+    }
+    float m = w[0];
+    if constexpr (SGPR == 0) m = m + (float)threadIdx.x * 1e-9f;  // per-lane: a vector register
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) x[c] = fma_c(m, y[c], x[c]);
+    }
+    float s = 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s += x[c];
+    if (s == -1.f) out[threadIdx.x] = s;
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void mb_mfma(float *out, int iters)
 {
@@ -72,7 +95,7 @@ using namespace stl;
 
 extern "C" int stencil_microbench(int kind, void *buf, int64_t bytes, void *stream_v, double *result)
 {
-    if (!result || kind < 0 || kind > 5) return fail(STENCIL_ERR_INVALID_ARG, "stencil_microbench: bad kind");
+    if (!result || kind < 0 || kind > 7) return fail(STENCIL_ERR_INVALID_ARG, "stencil_microbench: bad kind");
     if (kind == 0 && (!buf || bytes < 2 * 4096 || bytes % 32))
         return fail(STENCIL_ERR_INVALID_ARG, "stencil_microbench: copy needs an even buffer of >= 8 KiB");
     hipStream_t stream = (hipStream_t)stream_v;
@@ -85,6 +108,12 @@ extern "C" int stencil_microbench(int kind, void *buf, int64_t bytes, void *stre
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         return fail(STENCIL_ERR_OOM, "stencil_microbench: sink");
+    }
+    if (hipMemset(sink, 0, 256 * sizeof(double)) != hipSuccess) {  // the FMA kinds 6/7 read w[0] from it
+        (void)hipFree(sink);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(STENCIL_ERR_HIP, "stencil_microbench: memset");
     }
     const int grid = cus * 8;
     const int iters = 4096;
@@ -114,6 +143,16 @@ extern "C" int stencil_microbench(int kind, void *buf, int64_t bytes, void *stre
         case 4:
             hipLaunchKernelGGL(mb_mfma<STENCIL_F32>, dim3(grid), dim3(256), 0, stream, sink, iters);
             work = 4.0 * iters * 2.0 * 16 * 16 * 4 * (double)grid * 4;
+            break;
+        case 6:
+        case 7:
+            if (kind == 6)
+                hipLaunchKernelGGL(mb_fma32_operand<1>, dim3(grid), dim3(256), 0, stream, sink, iters,
+                                   (const float *)sink);
+            else
+                hipLaunchKernelGGL(mb_fma32_operand<0>, dim3(grid), dim3(256), 0, stream, sink, iters,
+                                   (const float *)sink);
+            work = 2.0 * 16 * iters * (double)grid * 256;
             break;
         case 5:
             hipLaunchKernelGGL(mb_mfma<STENCIL_BF16>, dim3(grid), dim3(256), 0, stream, sink, iters);
