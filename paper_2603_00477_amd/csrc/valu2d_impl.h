@@ -79,10 +79,13 @@ struct Valu2DCfg {
     // column-major (w[b][a]), each column of 2R+1 is scalar-loaded just before
     // its FMAs.  That frees 49-98 VGPRs for the T stages' accumulators
     // (Box-2D3R float64 T = 4: 232 instead of 340 registers, no spills, +30 %
-    // measured); at T <= 2 the weights pinned in VGPRs measured as fast or
-    // faster (float32 T = 2: 632 vs 478 GSt/s), so they stay there unless
-    // they need more than 128 dwords (r = 7: 225 weights).
-    static constexpr bool WPTR = SHAPE == STENCIL_BOX && sizeof(TC) * K > 192 && (T >= 3 || sizeof(TC) * K > 512);
+    // measured).  Float64 at T = 1 streams them too (Box-2D3R: 88 instead of
+    // 236 VGPRs; +9 % measured at 10240^2, equal at 8192^2).  At T = 2 the
+    // weights pinned in VGPRs measured faster (float32: 632 vs 478 GSt/s;
+    // float64: 340 vs 329), so they stay there unless they need more than 128
+    // dwords (r = 7: 225 weights).
+    static constexpr bool WPTR = SHAPE == STENCIL_BOX && sizeof(TC) * K > 192 &&
+                                 (T >= 3 || (sizeof(TC) == 8 && T == 1) || sizeof(TC) * K > 512);
 };
 
 // Weights in constant memory (scalar loads).
