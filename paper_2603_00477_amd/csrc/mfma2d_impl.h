@@ -246,8 +246,36 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
     if constexpr (KDIM != 4) {
         using Chunk = typename std::conditional<sizeof(TS) == 2, uint2, uint4>::type;
         constexpr int NCH = (LC + 3 + 3) / 4;  // chunks per row (start aligned down by up to 3)
-        constexpr int NE4 = (LRD * NCH + NT - 1) / NT;
+        // Chunk-to-lane map.  Row-major (lanes on consecutive chunks of a row:
+        // one contiguous segment per load) makes the column-major LDS writes
+        // of one instruction land 4 columns apart, on a few banks (measured:
+        // 69 % of LDS cycles in bank conflicts, Box-2D2R bf16 T = 4).  Blocks
+        // of 16 rows x 4 chunks (lane = row + 16 chunk) write 16 consecutive
+        // rows of 4 columns whose pitch is an odd number of 16-byte units:
+        // disjoint bank groups.  Measured on 16384^2: blocks are faster for
+        // the compensated split (two blocks written, +7-19 %) and for
+        // composite radii R >= 6 (+5-10 %); row-major is faster below
+        // (up to 15 % at T = 1), where staging latency rather than LDS
+        // throughput dominates.
+        constexpr bool SBLK = X3 || R >= 6;
+        constexpr int NRB = (LRD + 15) / 16, NCB = (NCH + 3) / 4, NBLK = NRB * NCB;
+        constexpr int NE4 = SBLK ? (NBLK + NW - 1) / NW : (LRD * NCH + NT - 1) / NT;  // chunks per thread
         constexpr int CB = NE4 < 8 ? NE4 : 8;
+        const int swv = tid >> 6, srr = tid & 15, scc = (tid >> 4) & 3;
+        auto chunk_at = [&](int it, int &row, int &ch) {
+            if constexpr (SBLK) {
+                const int blk = swv + NW * it;
+                const int rb = blk % NRB, cb = blk / NRB;
+                row = 16 * rb + srr;
+                ch = 4 * cb + scc;
+                return it < NE4 && blk < NBLK && row < LRD && ch < NCH;
+            } else {
+                const int e = tid + it * NT;
+                row = e / NCH;
+                ch = e - row * NCH;
+                return it < NE4 && e < LRD * NCH;
+            }
+        };
         const int cs = (c0 - R) & ~3;
         const int lead = (c0 - R) - cs;
         const bool fast = r0 - R >= 0 && r0 - R + LRD <= n0 && c0 - R >= 0 && cs + 4 * NCH <= n1 &&
@@ -260,16 +288,14 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
                 Chunk v[CB];
 #pragma unroll
                 for (int i = 0; i < CB; ++i) {
-                    const int e = tid + (e0 + i) * NT;
-                    const int row = e / NCH, ch = e - (e / NCH) * NCH;
-                    if (e0 + i < NE4 && e < LRD * NCH)
+                    int row, ch;
+                    if (chunk_at(e0 + i, row, ch))
                         v[i] = *reinterpret_cast<const Chunk *>(src + (int64_t)(r0 - R + row) * n1 + cs + 4 * ch);
                 }
 #pragma unroll
                 for (int i = 0; i < CB; ++i) {
-                    const int e = tid + (e0 + i) * NT;
-                    if (e0 + i >= NE4 || e >= LRD * NCH) break;
-                    const int row = e / NCH, ch = e - (e / NCH) * NCH;
+                    int row, ch;
+                    if (!chunk_at(e0 + i, row, ch)) continue;
                     uint16_t hi4[4], lo4[4];
                     if constexpr (sizeof(TS) == 2) {
                         hi4[0] = (uint16_t)(v[i].x & 0xffff);
