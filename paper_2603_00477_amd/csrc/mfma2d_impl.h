@@ -205,6 +205,14 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 
     __shared__ __attribute__((aligned(16))) OP lhi[Cfg::LDS_ELEMS];
     __shared__ __attribute__((aligned(16))) OP llo[X3 ? Cfg::LDS_ELEMS : 1];
+    // 16-bit operands: the whole A fragment table (NFRAG fragments of 64
+    // lanes) is copied to LDS with the input block when it fits in 24 KiB,
+    // so the column loop reads A from LDS instead of from L2
+    constexpr int NFRAG = band_total_frags(SHAPE, r, T, KDIM, 2);
+    constexpr int NAF = NFRAG * (X3 ? 2 : 1);
+    constexpr bool ALDS = KDIM != 4 && NAF <= 24;
+    using FRS = typename MT::FR;
+    __shared__ __attribute__((aligned(16))) FRS lA[ALDS ? NAF * 64 : 1];
 
     const int tid = threadIdx.x;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -230,13 +238,28 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 #pragma unroll
         for (int i = 0; i < NBMAX; ++i)
             if (i <= khi - klo) {
-                Ar[slot][i] = afr[(off + i) * 64 + lane];
-                if constexpr (X3) Alr[slot][i] = afr_lo[(off + i) * 64 + lane];
+                if constexpr (ALDS) {
+                    Ar[slot][i] = lA[(off + i) * 64 + lane];
+                    if constexpr (X3) Alr[slot][i] = lA[(NFRAG + off + i) * 64 + lane];
+                } else {
+                    Ar[slot][i] = afr[(off + i) * 64 + lane];
+                    if constexpr (X3) Alr[slot][i] = afr_lo[(off + i) * 64 + lane];
+                }
             }
     };
     if constexpr (KDIM == 4)
 #pragma unroll
         for (int j = 0; j < PF; ++j) load_col(j, j);
+    // A table for the LDS copy: loads in flight during the staging
+    constexpr int NAT = ALDS ? (NAF * 64 + NT - 1) / NT : 1;
+    FR ta[NAT];
+    if constexpr (ALDS) {
+#pragma unroll
+        for (int i = 0; i < NAT; ++i) {
+            const int e = tid + i * NT;
+            if (e < NAF * 64) ta[i] = e < NFRAG * 64 ? afr[e] : afr_lo[e - NFRAG * 64];
+        }
+    }
 
     // ---- 16-bit operands (bf16/f16 storage, or float storage split into
     // bf16 hi/lo), interior tile: rows are read in aligned chunks of four
@@ -424,6 +447,13 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
                     lhi[li] = (OP)(float)vals[i];
                 }
             }
+        }
+    }
+    if constexpr (ALDS) {
+#pragma unroll
+        for (int i = 0; i < NAT; ++i) {
+            const int e = tid + i * NT;
+            if (e < NAF * 64) lA[e] = ta[i];
         }
     }
     __syncthreads();
