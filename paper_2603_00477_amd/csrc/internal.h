@@ -100,6 +100,7 @@ const std::vector<KernelEntry> &valu3d_kernels();
 const std::vector<KernelEntry> &valu3d_box_kernels();  // boxes r >= 2, one step per pass
 const std::vector<KernelEntry> &valu2d_table_cases();  // r = 7, and r = 1 with T = 5..8
 const std::vector<KernelEntry> &mfma2d_table_cases();  // composite radius 7
+const std::vector<KernelEntry> &mfma3d_table_cases();  // composite radius 7, periodic
 const std::vector<KernelEntry> &generic_kernels();
 const std::vector<KernelEntry> &mfma2d_table_f64();
 const std::vector<KernelEntry> &mfma2d_table_f32();

@@ -182,7 +182,12 @@ void plan_model(stencil_plan_s *p)
 int resolve_path(stencil_plan_s *p)
 {
     const bool v = has_path(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T);
-    const bool m = has_path(STENCIL_PATH_MFMA, p->dtype, p->shape, p->d, p->r, p->T);
+    const bool m_built = has_path(STENCIL_PATH_MFMA, p->dtype, p->shape, p->d, p->r, p->T);
+    // a kernel-fused Dirichlet pass needs a VALU kernel of the same depth for
+    // its boundary band (launch_fixup)
+    const bool band_ok = p->boundary == STENCIL_PERIODIC || p->T == 1 ||
+                         find_kernel(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T) != nullptr;
+    const bool m = m_built && band_ok;
     int path = p->path_req;
     if (path == STENCIL_PATH_AUTO) {
         // the compensated mode exists only on the matrix path (its VALU
@@ -192,8 +197,12 @@ int resolve_path(stencil_plan_s *p)
     }
     if (path == STENCIL_PATH_VALU && !v)
         return fail(STENCIL_ERR_UNSUPPORTED, "VALU path not built for this dtype/shape/d/r");
-    if (path == STENCIL_PATH_MFMA && !m)
+    if (path == STENCIL_PATH_MFMA && !m_built)
         return fail(STENCIL_ERR_UNSUPPORTED, "MFMA path not built for this dtype/shape/d/r/T");
+    if (path == STENCIL_PATH_MFMA && !band_ok)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "Dirichlet MFMA plan needs a fused VALU kernel of the same T for its boundary band; "
+                    "use a periodic boundary or another T");
     if (p->dtype == STENCIL_F32_BF16X3 && path != STENCIL_PATH_MFMA)
         return fail(STENCIL_ERR_UNSUPPORTED, "bf16x3 is an MFMA-only mode");
     if (path == STENCIL_PATH_MFMA && p->boundary == STENCIL_PERIODIC)

@@ -52,6 +52,20 @@ def test_periodic_mfma_needs_room():
     assert e.value.status == "INVALID_ARG"
 
 
+def test_dirichlet_mfma_needs_a_band_kernel():
+    # Box-3D1R fused 7 deep exists on the matrix path only: a Dirichlet plan
+    # would have no kernel for its boundary band, a periodic one is accepted
+    w = [1 / 27] * 27
+    with pytest.raises(stl.StencilError) as e:
+        stl.Plan("box", 3, 1, w, (32, 32, 32), T=7, dtype="f32", boundary="dirichlet", path="mfma")
+    assert e.value.status == "UNSUPPORTED" and "boundary band" in str(e.value)
+    p = stl.Plan("box", 3, 1, w, (32, 32, 32), T=7, dtype="f32", boundary="periodic", path="mfma")
+    assert p.info()["path_name"] == "mfma"
+    # the model predicts the vector units for this case; without a fused VALU
+    # kernel of depth 7 the automatic choice still runs it there (T = 1 passes)
+    assert stl.Plan("box", 3, 1, w, (32, 32, 32), T=7, dtype="f32", boundary="dirichlet").info()["path_name"] == "valu"
+
+
 def test_bf16x3_is_mfma_only():
     with pytest.raises(stl.StencilError) as e:
         stl.Plan("box", 2, 2, [1 / 25] * 25, (64, 64), T=1, dtype="bf16x3", path="valu")

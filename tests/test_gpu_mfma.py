@@ -142,6 +142,19 @@ def test_mfma3d(stl, shape, r, T, dt, boundary):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
+def test_mfma3d_radius7_composite(stl):
+    """Composite radius 7 in 3D (the paper's Box-3D1R fused 7 deep, float):
+    two full passes and a one-step remainder on a periodic grid with ragged
+    in-plane tiles and the minimum 2rT + 1 planes."""
+    dims = (15, 37, 70)
+    u0, u0r, t, w = case_inputs("box", 3, 1, dims, "f32", seed=6900)
+    p = stl.Plan("box", 3, 1, w, dims, T=7, dtype="f32", path="mfma", boundary="periodic")
+    assert p.info()["path_name"] == "mfma"
+    got = run_gpu(p, t, 15)
+    ref = oracle("box", 3, 1, w, u0, 15, "periodic")
+    assert rel_inf(got, ref) <= TOL["f32"]
+
+
 @pytest.mark.parametrize("shape,r,T,dims", [("box", 1, 3, (9, 11, 13)), ("star", 2, 2, (9, 20, 70))])
 def test_mfma3d_small_periodic(stl, shape, r, T, dims):
     """Periodic 3D grids smaller than one in-plane tile."""
