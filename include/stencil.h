@@ -110,7 +110,10 @@ typedef struct {
  * Path AUTO resolves to the model's predicted winner among the paths built
  * for this combination.
  * Errors: INVALID_ARG (d not in {2,3}, r < 1, T < 1, NULL or non-finite
- * weights, dims < 1), UNSUPPORTED, OOM, HIP.  On error *plan is NULL.
+ * weights, dims < 1), UNSUPPORTED (no kernel for the combination; also a
+ * Dirichlet MFMA plan with T > 1 whose boundary band, which kernel fusion
+ * does not compute exactly, has no fused VALU kernel of the same T to redo
+ * it, e.g. Box-3D1R T = 7), OOM, HIP.  On error *plan is NULL.
  */
 int stencil_plan(stencil_plan_t *plan, int shape, int d, int r, const double *weights,
                  const int64_t *dims, int T, int dtype, int boundary);
