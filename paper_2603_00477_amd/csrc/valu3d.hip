@@ -3,8 +3,10 @@
 //
 // A workgroup of TX x TY threads owns an extended in-plane tile of
 // (TY*WY) x (TX*W) points (each thread WY rows x W consecutive columns) and
-// streams down a segment of planes.  The tile carries a skirt of R*T points on
-// every side for the later steps; the valid output tile is the interior.
+// streams down a segment of planes.  A fused pass's tile carries a skirt of
+// R*T points on every side for the later steps; the valid output tile is the
+// interior.  A one-step pass stages the plane's R-point halo around the tile
+// as well and has no skirt.
 // The step pipeline is the one of the 2D kernel with rows replaced by planes:
 // stage 0 writes input plane k to an LDS plane buffer; stage s reads the plane
 // stage s-1 wrote one iteration earlier, scatters it into 2R+1 rotating
@@ -44,14 +46,25 @@ struct Valu3DCfg {
     static constexpr int NT = TX * TY;
     static constexpr int PY = TY * WY;                      // extended rows
     static constexpr int PX = TX * W;                       // extended columns
-    static constexpr int EY = R * T;                        // row skirt
-    static constexpr int EX = ((R * T + W - 1) / W) * W;    // column skirt (vector aligned)
+    // One-step passes (HALO) stage the input plane's R-point halo around the
+    // tile as well, so the tile needs no skirt: every computed point is an
+    // output (+15-26 % measured at 512^3).  Fused passes stage the tile only
+    // and carry a skirt of R T points (staging the halo there, for a skirt of
+    // R (T - 1), measured 9-25 % slower on most fused variants).
+    static constexpr bool HALO = T == 1;
+    static constexpr int EY = HALO ? 0 : R * T;                     // row skirt
+    static constexpr int EX = HALO ? 0 : ((R * T + W - 1) / W) * W; // column skirt (vector aligned)
     static constexpr int PADX = ((R + W - 1) / W) * W;      // LDS column pad
     static constexpr int LDX = PX + 2 * PADX;               // LDS row pitch
     static constexpr int LROWS = PY + 2 * R;                // LDS rows (R pad each side)
     static constexpr int PLANE = LROWS * LDX;
     static constexpr int Q = 2 * R + 1;
     static constexpr int U = Q;                             // planes prefetched ahead
+    // halo points of a staged plane: rows [-R, PY+R) x columns [-R, PX+R)
+    // outside the PY x PX extended tile, NH per thread
+    static constexpr int HROW = PX + 2 * R;
+    static constexpr int NHALO = 2 * R * HROW + 2 * R * PY;
+    static constexpr int NH = HALO ? (NHALO + NT - 1) / NT : 1;
     // 0: scalar registers; 1: pinned vector registers.  Float32 FMAs run ~35 %
     // slower with a scalar-register operand on gfx950, so float32 sets go to
     // vector registers for r <= 2 (+8-13 % measured); at r = 3 the extra
@@ -183,6 +196,47 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
 #pragma unroll
     for (int u = 0; u < U; ++u)
         if (u < KTOT) load_plane(u, ring[u]);
+
+    // this thread's halo points: LDS offset in a plane (-1: none), source
+    // offset in a plane (-1: outside a Dirichlet grid, value h)
+    constexpr int NH = Cfg::NH, HROW = Cfg::HROW;
+    int h_lds[NH];
+    int64_t h_src[NH];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        h_lds[i] = -1;
+        h_src[i] = -1;
+        if constexpr (!Cfg::HALO) continue;
+        const int e = tid + i * NT;
+        int lr = 0, lc = 0;
+        if (e < R * HROW) {
+            lr = -R + e / HROW;
+            lc = -R + e % HROW;
+        } else if (e < 2 * R * HROW) {
+            lr = Cfg::PY + (e - R * HROW) / HROW;
+            lc = -R + (e - R * HROW) % HROW;
+        } else {
+            const int e3 = e - 2 * R * HROW, m = e3 % (2 * R);
+            lr = e3 / (2 * R);
+            lc = m < R ? -R + m : Cfg::PX + m - R;
+        }
+        h_lds[i] = e < Cfg::NHALO ? (R + lr) * LDX + PADX + lc : -1;
+        const int gr = y0 - Cfg::EY + lr, gc = x0 - Cfg::EX + lc;
+        const bool in = gr >= 0 && gr < n1 && gc >= 0 && gc < n2;
+        h_src[i] = periodic ? (int64_t)wrap(gr, n1) * n2 + wrap(gc, n2) : (in ? (int64_t)gr * n2 + gc : -1);
+    }
+    // halo values of plane k (issued one plane ahead of their use)
+    auto load_halo = [&](int k, TS (&hv)[NH]) {
+        if constexpr (!Cfg::HALO) return;
+        const int z = zbase + k;
+        const bool zin = z >= 0 && z < n0;
+        const TS *pl = src + (int64_t)(periodic ? wrap(z, n0) : (zin ? z : 0)) * n1 * n2;
+#pragma unroll
+        for (int i = 0; i < NH; ++i)
+            hv[i] = (h_lds[i] >= 0 && h_src[i] >= 0 && (periodic || zin)) ? pl[h_src[i]] : hs;
+    };
+    TS hnext[NH];
+    load_halo(0, hnext);
     __syncthreads();
 
     // LDS position of this thread's first point inside a plane buffer
@@ -200,6 +254,13 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
                 for (int i = 0; i < WY; ++i)
 #pragma unroll
                     for (int j = 0; j < W; ++j) w0[i * LDX + j] = to_compute<TC>(ring[u][i].e[j]);
+                if constexpr (Cfg::HALO) {
+                    TC *h0 = &lds[0][par][0];
+#pragma unroll
+                    for (int i = 0; i < NH; ++i)
+                        if (h_lds[i] >= 0) h0[h_lds[i]] = to_compute<TC>(hnext[i]);
+                    if (k + 1 < KTOT) load_halo(k + 1, hnext);
+                }
                 if (k + U < KTOT) load_plane(k + U, ring[u]);
             }
 #pragma unroll
