@@ -47,13 +47,14 @@ struct Valu3DCfg {
     static constexpr int PY = TY * WY;                      // extended rows
     static constexpr int PX = TX * W;                       // extended columns
     // One-step passes (HALO) stage the input plane's R-point halo around the
-    // tile as well, so the tile needs no skirt: every computed point is an
-    // output (+15-26 % measured at 512^3).  Fused passes stage the tile only
-    // and carry a skirt of R T points (staging the halo there, for a skirt of
-    // R (T - 1), measured 9-25 % slower on most fused variants).
+    // tile as well (prefetched U planes ahead with the tile), so the tile
+    // needs no skirt: every computed point is an output (+25-31 % measured at
+    // 512^3).  Fused passes stage the tile only and carry a skirt of R T
+    // points (staging the halo there, for a skirt of R (T - 1), measured up
+    // to 7 % slower at T = 2 and up to 25 % at T = 3).
     static constexpr bool HALO = T == 1;
-    static constexpr int EY = HALO ? 0 : R * T;                     // row skirt
-    static constexpr int EX = HALO ? 0 : ((R * T + W - 1) / W) * W; // column skirt (vector aligned)
+    static constexpr int EY = HALO ? 0 : R * T;           // row skirt
+    static constexpr int EX = ((EY + W - 1) / W) * W;     // column skirt (vector aligned)
     static constexpr int PADX = ((R + W - 1) / W) * W;      // LDS column pad
     static constexpr int LDX = PX + 2 * PADX;               // LDS row pitch
     static constexpr int LROWS = PY + 2 * R;                // LDS rows (R pad each side)
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
         const bool in = gr >= 0 && gr < n1 && gc >= 0 && gc < n2;
         h_src[i] = periodic ? (int64_t)wrap(gr, n1) * n2 + wrap(gc, n2) : (in ? (int64_t)gr * n2 + gc : -1);
     }
-    // halo values of plane k (issued one plane ahead of their use)
+    // halo values of plane k (issued U planes ahead of their use)
     auto load_halo = [&](int k, TS (&hv)[NH]) {
         if constexpr (!Cfg::HALO) return;
         const int z = zbase + k;
@@ -235,8 +236,10 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
         for (int i = 0; i < NH; ++i)
             hv[i] = (h_lds[i] >= 0 && h_src[i] >= 0 && (periodic || zin)) ? pl[h_src[i]] : hs;
     };
-    TS hnext[NH];
-    load_halo(0, hnext);
+    TS hring[U][NH];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (u < KTOT) load_halo(u, hring[u]);
     __syncthreads();
 
     // LDS position of this thread's first point inside a plane buffer
@@ -258,8 +261,8 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
                     TC *h0 = &lds[0][par][0];
 #pragma unroll
                     for (int i = 0; i < NH; ++i)
-                        if (h_lds[i] >= 0) h0[h_lds[i]] = to_compute<TC>(hnext[i]);
-                    if (k + 1 < KTOT) load_halo(k + 1, hnext);
+                        if (h_lds[i] >= 0) h0[h_lds[i]] = to_compute<TC>(hring[u][i]);
+                    if (k + U < KTOT) load_halo(k + U, hring[u]);
                 }
                 if (k + U < KTOT) load_plane(k + U, ring[u]);
             }
