@@ -150,6 +150,20 @@ def test_valu3d(stl, shape, r, T, dt, boundary):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 5, 7), (2, 9, 70), (9, 17, 3)])
+@pytest.mark.parametrize("shape,r", [("star", 2), ("box", 1), ("star", 3)])
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+def test_valu3d_one_step_small_grids(stl, dims, shape, r, boundary):
+    """One-step 3D passes stage the plane halo around the tile: grids smaller
+    than the halo (a periodic halo wraps several times; a Dirichlet one is
+    mostly h) and thinner than one tile in every direction."""
+    u0, u0r, t, w = case_inputs(shape, 3, r, dims, "f64", seed=5300 + 10 * r + sum(dims))
+    p = stl.Plan(shape, 3, r, w, dims, T=1, dtype="f64", path="valu", boundary=boundary, halo=0.375)
+    got = run_gpu(p, t, 3)
+    ref = oracle(shape, 3, r, w, u0, 3, boundary, 0.375)
+    assert rel_inf(got, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("r", [2, 3])
 def test_valu3d_large_box_many_tiles(stl, r, dt):
