@@ -7,8 +7,10 @@
 // tiles (16V rows x 16 columns).  The input block the workgroup needs
 // ((16V + 2R) x (16 NW + 2R) points, halo included, boundary rule applied) is
 // staged once in LDS in the operand type.  For every kernel column b the wave
-// loads that column's A fragments (lane-ordered on the host, L2-resident) and
-// issues one MFMA per (tile, structurally non-zero k-block).  With KDIM = 4
+// loads that column's A fragments (lane-ordered on the host, L2-resident; the
+// 16-bit kernels copy the whole fragment table to LDS with the input block
+// when it fits in 24 KiB) and issues one MFMA per (tile, structurally non-zero
+// k-block).  With KDIM = 4
 // (f64/f32) a B fragment of rows 4q..4q+3 serves every stacked tile whose
 // k-block lands on it.  With KDIM = 32 (bf16/f16) the LDS block is stored
 // column-major so each lane's 8 consecutive rows are one 16-byte read.
