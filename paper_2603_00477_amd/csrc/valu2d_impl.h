@@ -234,6 +234,13 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
     // block's accumulators after its FMAs keeps the next wait behind them
     // (volatile asm statements keep their order), so each fetch overlaps a
     // whole block of FMAs and at most two columns are live.
+    // float32: FMAs run faster on vector-register operands (one move per
+    // weight).  For r >= 5 a column moves to vector registers when it becomes
+    // current, after the previous block's FMAs, so its scalar loads complete
+    // under them (moving at the fetch waits for each load at once and
+    // serialises them: Box-2D7R 129 -> 135 GSt/s); for r = 3 moving at the
+    // fetch measured as fast or slightly faster.
+    constexpr bool LATE_MOVE = sizeof(TC) == 4 && R >= 5;
     TC wcur[Q], wnxt[Q];
     auto fetch_col = [&](int b, TC *dstw, TC after) {
         int off = b * Q;
@@ -242,11 +249,18 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
 #pragma unroll
         for (int e = 0; e < Q; ++e) {
             dstw[e] = wp[off + e];
-            // float32: FMAs run faster on vector-register operands (one move each)
-            if constexpr (sizeof(TC) == 4) asm volatile("" : "+v"(dstw[e]));
+            if constexpr (sizeof(TC) == 4 && !LATE_MOVE) asm volatile("" : "+v"(dstw[e]));
         }
     };
-    if constexpr (Cfg::WPTR) fetch_col(0, wcur, TC(0));
+    auto to_vgpr = [&](TC *wv) {
+        if constexpr (LATE_MOVE)
+#pragma unroll
+            for (int e = 0; e < Q; ++e) asm volatile("" : "+v"(wv[e]));
+    };
+    if constexpr (Cfg::WPTR) {
+        fetch_col(0, wcur, TC(0));
+        to_vgpr(wcur);
+    }
 
     for (int kb = 0; kb < KTOT; kb += U) {
 #pragma unroll
@@ -286,6 +300,7 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                                 for (int j = 0; j < W; ++j) asm volatile("" ::"v"(acc[s - 1][q][j]));
 #pragma unroll
                             for (int e = 0; e < Q; ++e) wcur[e] = wnxt[e];
+                            to_vgpr(wcur);
                         }
                     } else {
 #pragma unroll
