@@ -2,7 +2,7 @@
 
 Two commands:
 
-  python -m paper_2603_00477_amd.counters run [--n2 N] [--n3 N] [--set model|ai_t]
+  python -m paper_2603_00477_amd.counters run [--n2 N] [--n3 N] [--set model|ai_t|p16]
       Runs one pass (T fused steps) of each listed variant on the GPU, two
       times, so that a rocprofv3 counter pass records every kernel.  Prints a
       JSON line per variant with the grid size and the model's C, M, I.
@@ -52,6 +52,8 @@ def run(n2: int, n3: int, which: str = "model"):
 
     if which == "ai_t":
         todo = [(2, v) for v in VARIANTS_AI_T]
+    elif which == "p16":
+        todo = [(2, v) for v in VARIANTS_16]
     else:
         todo = [(2, v) for v in VARIANTS_2D] + [(3, v) for v in VARIANTS_3D] + [(2, v) for v in VARIANTS_16]
     x_cache = {}
@@ -151,9 +153,9 @@ def main(argv=None):
     r = sub.add_parser("run")
     r.add_argument("--n2", type=int, default=4096)
     r.add_argument("--n3", type=int, default=256)
-    r.add_argument("--set", default="model", choices=["model", "ai_t"],
+    r.add_argument("--set", default="model", choices=["model", "ai_t", "p16"],
                    help="model: every 8192^2 / 512^3 / precision variant; ai_t: Box/Star-2D1R "
-                        "float64 at T = 1..8")
+                        "float64 at T = 1..8; p16: the 16-bit and compensated MFMA variants only")
     rep = sub.add_parser("report")
     rep.add_argument("fetch")
     rep.add_argument("write")
