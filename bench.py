@@ -333,10 +333,13 @@ def section_c4(stl, args):
         p.close()
         return snaps, ms_total
 
+    golden = load_precision_windows(w)
     ref0 = torch.from_numpy(u0).to("cuda")
     ref_snaps, ref_ms = sweep("f64", "valu", 2, ref0)
     log(f"f64 reference: {npts * 1000 / (ref_ms * 1e-3) / 1e9:.1f} GSt/s")
     out = {"reference": dict(dtype="f64", path="valu", T=2, gst=npts * 1000 / (ref_ms * 1e-3) / 1e9)}
+    if golden:
+        out["reference"]["oracle_window_err_1000"] = window_err(ref_snaps[-1], golden, "f64")
     modes = [("bf16", "mfma", 4), ("f16", "mfma", 4), ("bf16x3", "mfma", 4), ("bf16", "mfma", 2),
              ("bf16", "valu", 2), ("f16", "valu", 2), ("f32", "valu", 2), ("f32", "mfma", 4)]
     for dt, path, T in modes:
@@ -347,20 +350,54 @@ def section_c4(stl, args):
             out[f"{dt}-{path}-T{T}"] = dict(error=str(e))
             continue
         errs = []
-        for k, (s, rsnap) in enumerate(zip(snaps, ref_snaps)):
-            d = (s.to(torch.float64) - rsnap)
+        for k, (s_, rsnap) in enumerate(zip(snaps, ref_snaps)):
+            d = (s_.to(torch.float64) - rsnap)
             errs.append(float(d.abs().max() / rsnap.abs().max()))
             del d
         m = stl.model_predict("box", 2, 2, T, dt)
-        out[f"{dt}-{path}-T{T}"] = dict(gst=npts * 1000 / (ms * 1e-3) / 1e9, err_every_100=errs,
-                                        predicted_winner=m["winner"], scenario=m["scenario"],
-                                        predicted_gst=m["gst_valu"] if path == "valu" else m["gst_mfma"])
-        log(f"{dt}-{path}-T{T}: {out[f'{dt}-{path}-T{T}']['gst']:.1f} GSt/s, err@1000 {errs[-1]:.2e}")
+        row = dict(gst=npts * 1000 / (ms * 1e-3) / 1e9, err_every_100=errs,
+                   predicted_winner=m["winner"], scenario=m["scenario"],
+                   predicted_gst=m["gst_valu"] if path == "valu" else m["gst_mfma"])
+        if golden:
+            # end-to-end: oracle on the float64 data; arithmetic: oracle on
+            # the storage-rounded data (both after 1000 steps, on the stored
+            # window), relative to the window's max |u|
+            row["oracle_e2e_1000"] = window_err(snaps[-1], golden, "f64")
+            row["oracle_arith_1000"] = window_err(snaps[-1], golden,
+                                                  {"bf16x3": "f32"}.get(dt, dt))
+        out[f"{dt}-{path}-T{T}"] = row
+        log(f"{dt}-{path}-T{T}: {row['gst']:.1f} GSt/s, err@1000 vs f64 sweep {errs[-1]:.2e}"
+            + (f", vs oracle window: end-to-end {row['oracle_e2e_1000']:.2e}, arithmetic "
+               f"{row['oracle_arith_1000']:.2e}" if golden else ""))
         del snaps, x0
         torch.cuda.empty_cache()
     del ref_snaps, ref0
     torch.cuda.empty_cache()
     return out
+
+
+def load_precision_windows(w):
+    """FP64 oracle values of the precision workload after 1000 steps on one
+    window (written by tests/golden/make_precision_windows.py from the
+    oracle), or None if absent or made for other weights."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "precision_windows_16384.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    if not np.array_equal(np.asarray(g["weights"]), w):
+        return None
+    return g
+
+
+def window_err(snap, golden, key):
+    import numpy as np
+
+    lo, hi = golden["lo"], golden["hi"]
+    got = snap[lo[0]:hi[0], lo[1]:hi[1]].double().cpu().numpy()
+    ref = np.asarray(golden["windows"][key]["values"])
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
 
 # ---------------------------------------------------------------- served stream
@@ -473,7 +510,58 @@ def cpu_baseline(n, budget_s):
     core.run("box", 2, 3, w, u0, k, "dirichlet", 0.0)
     dt = time.perf_counter() - t0
     return dict(value=n * n * k / dt / 1e9, unit="GStencil/s", cores=threads, kind="oracle",
-                sample=f"Box-2D3R f64 {n}x{n}, {k} time steps (of 100), zero Dirichlet halo")
+                sample=f"Box-2D3R f64 {n}x{n}, {k} time steps (of 100), zero Dirichlet halo",
+                cpu_model=cpu_model(), nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _smi_clocks():
+    """Current shader (sclk) and memory (mclk) clocks in MHz from rocm-smi,
+    or None."""
+    import subprocess
+
+    try:
+        p = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=30)
+        data = json.loads(p.stdout)
+    except Exception:
+        return None
+    out = {}
+    for card in data.values():
+        if not isinstance(card, dict):
+            continue
+        for k, v in card.items():
+            m = re.search(r"(\d+)\s*Mhz", str(v), re.I)
+            for name in ("sclk", "mclk", "fclk", "socclk"):
+                if m and k.lower().startswith(name) and "speed" in k.lower():
+                    out[f"{name}_mhz"] = int(m.group(1))
+        break
+    return out or None
+
+
+def clocks_under_load(busy):
+    """Clocks sampled while `busy()` keeps the GPU working (the reading is
+    taken in another thread during about two seconds of work)."""
+    import threading
+
+    box = {}
+    th = threading.Thread(target=lambda: box.setdefault("c", _smi_clocks()))
+    t0 = time.perf_counter()
+    th.start()
+    while th.is_alive() and time.perf_counter() - t0 < 30:
+        busy()
+    th.join()
+    return box.get("c")
 
 
 def source_hash():
@@ -498,6 +586,78 @@ def recorded_traffic(variant):
     return float(m.group(1)) if m else None
 
 
+# ---------------------------------------------------------------- output
+def _r(x, nd=1):
+    return None if x is None else round(float(x), nd)
+
+
+def _sig(x, nd=3):
+    return None if x is None else float(f"{float(x):.{nd}g}")
+
+
+def summaries(variants, mcheck, precision, serving, cases):
+    """One-line summaries of every section for the JSON line (the full
+    per-variant detail goes to --json-out / stderr)."""
+    out = {}
+    if variants:
+        out["variants_gst"] = {k.replace("-2d3r", ""): _r(r["gst"]) for k, r in variants.items()}
+    if mcheck:
+        out["model_check"] = f"{mcheck['agree']}/{mcheck['total']}"
+    if precision:
+        out["precision"] = {k: [_r(v["gst"]), _sig(v.get("oracle_e2e_1000", v["err_every_100"][-1])),
+                                _sig(v.get("oracle_arith_1000"))]
+                            for k, v in precision.items() if k != "reference" and "gst" in v}
+    if serving:
+        out["serving"] = {
+            "served": [_r(serving["served"]["p50_ms"], 2), _r(serving["served"]["p99_ms"], 2),
+                       _r(serving["served"]["gst"])],
+            "fifo": [_r(serving["fifo"]["p50_ms"], 2), _r(serving["fifo"]["p99_ms"], 2),
+                     _r(serving["fifo"]["gst"])],
+            "capacity_gst": [_r(serving["served_capacity"]["gst"]), _r(serving["fifo_capacity"]["gst"])]}
+    if cases:
+        out["paper_cases"] = {k: [_r(c.get("valu", {}).get("gst")), _r(c.get("mfma", {}).get("gst")),
+                                  c["predicted"], c.get("measured")] for k, c in cases.items()}
+    return out
+
+
+SUMMARY_KEYS = {
+    "variants_gst": "GStencil/s per 8192^2 variant (shape-dtype-T-path)",
+    "precision": "16384^2 Box-2D2R, 1000 steps: [GStencil/s, end-to-end error, arithmetic error] "
+                 "(relative, against the FP64 oracle on a window after 1000 steps)",
+    "serving": "served stream: [p50 ms, p99 ms, GStencil/s] at 0.8 load; capacity_gst [served, fifo]",
+    "paper_cases": "Table 3 cases at 10240^2 / 1024^3: [VALU, MFMA GStencil/s, predicted, measured]",
+}
+
+
+def compact_line(args, head_name, head, hv, roof, cpu, clocks, summ):
+    """The JSON line on stdout (kept under 4 KB)."""
+    line = {
+        "metric": "GStencil/s",
+        "value": _r(head.get("gst"), 2),
+        "unit": "GStencil/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": _r(head.get("ms_per_sweep"), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": hv["dtype"] if hv else None,
+        "data": "synthetic",
+        "config": {"workload": (f"Box-2D3R {args.n}x{args.n} {hv['dtype']}, {args.time_steps} time steps "
+                                f"per step, zero Dirichlet halo, T={hv['T']}, {head['path']} path")
+                   if hv else None,
+                   "step": f"one sweep of {args.time_steps} time steps over the whole grid"},
+        "roofline": ({k: (_sig(v, 4) if isinstance(v, float) else v) for k, v in roof.items()}
+                     if roof else None),
+        "cpu_baseline": ({k: (_sig(v, 4) if isinstance(v, float) else v) for k, v in cpu.items()}
+                         if cpu else None),
+        "clocks": clocks,
+        "summary": summ,
+    }
+    return json.dumps(line, separators=(",", ":"))
+
+
 # ---------------------------------------------------------------- main
 def main():
     args = parse()
@@ -518,49 +678,55 @@ def main():
     box64 = {k: r for k, r in ok.items() if k.startswith("box-2d3r-f64")}
     pool = box64 or ok
     head_name = max(pool, key=lambda k: pool[k]["gst"]) if pool else None
+    hv = next((v for v in headline_variants(args.n, args.time_steps) if v["name"] == head_name), None)
+    clocks = None
+    if hv:
+        clocks = headline_clocks(stl, args, hv)
     c3 = section_c3(stl, args) if "c3" in sections else {}
     c4 = section_c4(stl, args) if "c4" in sections else None
     c5 = section_serving(stl, args) if "c5" in sections else None
     cases = section_cases(stl, args) if "cases" in sections else None
     cpu = None if args.no_cpu or not head_name else cpu_baseline(args.n, args.cpu_seconds)
     head = ok.get(head_name, {})
-    hv = next((v for v in headline_variants(args.n, args.time_steps) if v["name"] == head_name), None)
     roof = dict(head.get("roofline", {}))
     if roof:
         roof["traffic"] = recorded_traffic(head_name)
-    line = {
-        "metric": "GStencil/s (Box-2D3R 8192^2 f64, 100 steps, best path/T)",
-        "value": head.get("gst"),
-        "unit": "GStencil/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head.get("ms_per_sweep"),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": hv["dtype"] if hv else None,
-        "data": "synthetic",
-        "config": {"workload": (f"Box-2D3R {args.n}x{args.n} {hv['dtype']}, {args.time_steps} steps, "
-                                f"Dirichlet h=0, T={hv['T']}, {head['path']} path") if hv else None,
-                   "grid": [args.n, args.n], "time_steps": args.time_steps,
-                   "T": hv["T"] if hv else None, "path": head.get("path")},
-        "roofline": roof or None,
-        "cpu_baseline": cpu,
-        "variants": {k: {"gst": r["gst"], "path": r["path"], "T": r["T"], "frac": r["roofline"]["frac"],
-                         "bound": r["roofline"]["bound"], "predicted_gst": r["predicted_gst"],
-                         "scenario": r["scenario"], "launch_ms": r["launch_ms"]}
-                     for k, r in ok.items()},
-        "model_check": model_check(c2, c3) if (c2 or c3) else None,
-        "precision": c4,
-        "serving": c5,
-        "paper_cases": cases,
+    mcheck = model_check(c2, c3) if (c2 or c3) else None
+    detail = {
+        "headline": head_name, "roofline": roof or None, "cpu_baseline": cpu, "clocks": clocks,
+        "variants": ok, "model_check": mcheck, "precision": c4, "serving": c5, "paper_cases": cases,
+        "summary_keys": SUMMARY_KEYS,
     }
-    s = json.dumps(line)
-    print(s, flush=True)
+    s = json.dumps(detail)
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(s + "\n")
+    else:
+        print("# detail " + s, file=sys.stderr, flush=True)
+    print(compact_line(args, head_name, head, hv, roof, cpu, clocks,
+                       summaries(ok, mcheck, c4, c5, cases)), flush=True)
+
+
+def headline_clocks(stl, args, hv):
+    """sclk / mclk while the headline plan runs."""
+    import torch
+
+    import stencil_inputs as si
+
+    n = args.n
+    x = torch.rand((n, n), device="cuda", dtype=stl.torch_dtype(hv["dtype"]))
+    y = torch.empty_like(x)
+    w = si.normalised_weights(hv["K"], seed=si.weight_seed(2, 0))
+    p = stl.Plan(hv["shape"], 2, hv["r"], w, (n, n), T=hv["T"], dtype=hv["dtype"], path=hv["path"])
+
+    def busy():
+        p.run(x, y, args.time_steps)
+        torch.cuda.synchronize()
+
+    c = clocks_under_load(busy)
+    p.close()
+    log(f"clocks under load: {c}")
+    return c
 
 
 if __name__ == "__main__":

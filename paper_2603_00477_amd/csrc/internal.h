@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/stencil.h"
@@ -51,8 +52,9 @@ struct PassArgs {
 // Device copies of small host tables (job lists of batched launches).  put()
 // copies `bytes` into a pinned host region and enqueues its upload on
 // `stream`.  Each begin() .. end() bracket (one batch call) fills one slot of
-// a ring; its regions stay valid until the slot comes round again, and
-// begin() waits only if the batch that last used that slot is still queued.
+// a ring; its regions stay valid until the slot comes round again (also when
+// the slot had to grow in between), and begin() waits only if the batch that
+// last used that slot is still queued.
 class BatchStaging {
 public:
     hipError_t begin(hipStream_t stream);
@@ -71,8 +73,10 @@ private:
         size_t cap = 0, used = 0;
         hipEvent_t done = nullptr;
         bool pending = false;
+        // buffers replaced by grow() during the current batch (host, device)
+        std::vector<std::pair<uint8_t *, uint8_t *>> retired;
     };
-    hipError_t grow(Slot &s, size_t need, hipStream_t stream);
+    hipError_t grow(Slot &s, size_t need);
     Slot slots_[kSlots];
     int cur_ = kSlots - 1;
 };

@@ -18,28 +18,34 @@ hipError_t BatchStaging::begin(hipStream_t stream)
         if (e != hipSuccess) return e;
         s.pending = false;
     }
+    // buffers the slot outgrew during that batch are no longer referenced
+    for (auto &old : s.retired) {
+        (void)hipHostFree(old.first);
+        (void)hipFree(old.second);
+    }
+    s.retired.clear();
     s.used = 0;
     return hipSuccess;
 }
 
-hipError_t BatchStaging::grow(Slot &s, size_t need, hipStream_t stream)
+hipError_t BatchStaging::grow(Slot &s, size_t need)
 {
-    // regions of this slot handed out in this call may still be read by
-    // kernels already queued
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return e;
+    // Regions of this slot handed out earlier in the same batch call stay
+    // valid: kernels already queued, and launches of this call not yet
+    // issued, may read them.  The old buffers are retired, not freed, and
+    // released by the next begin() on this slot, after the slot's event has
+    // shown that the whole batch finished.
     size_t cap = s.cap ? s.cap : (size_t)1 << 16;
     while (cap < need) cap *= 2;
     uint8_t *h = nullptr, *d = nullptr;
-    e = hipHostMalloc((void **)&h, cap, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&h, cap, hipHostMallocDefault);
     if (e != hipSuccess) return e;
     e = hipMalloc((void **)&d, cap);
     if (e != hipSuccess) {
         (void)hipHostFree(h);
         return e;
     }
-    if (s.host) (void)hipHostFree(s.host);
-    if (s.dev) (void)hipFree(s.dev);
+    if (s.host || s.dev) s.retired.emplace_back(s.host, s.dev);
     s.host = h;
     s.dev = d;
     s.cap = cap;
@@ -52,7 +58,7 @@ hipError_t BatchStaging::put(const void *host, size_t bytes, void **dev, hipStre
     Slot &s = slots_[cur_];
     const size_t off = (s.used + 255) & ~(size_t)255;
     if (off + bytes > s.cap) {
-        hipError_t e = grow(s, off + bytes > 2 * s.cap ? off + bytes : 2 * s.cap, stream);
+        hipError_t e = grow(s, bytes > 2 * s.cap ? bytes : 2 * s.cap);
         if (e != hipSuccess) return e;
         return put(host, bytes, dev, stream);
     }
@@ -80,6 +86,10 @@ BatchStaging::~BatchStaging()
 {
     // process teardown: the runtime may already be gone, errors are ignored
     for (Slot &s : slots_) {
+        for (auto &old : s.retired) {
+            (void)hipHostFree(old.first);
+            (void)hipFree(old.second);
+        }
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
         if (s.done) (void)hipEventDestroy(s.done);

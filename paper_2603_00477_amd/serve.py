@@ -12,7 +12,10 @@ time.  A scheduler thread:
     while others run join the next round and their work shares launches with
     the jobs already running;
   * completes a job when the event recorded after its last round has fired,
-    hands its output tensor to the caller and frees its budget.
+    hands its output tensor to the caller and frees the rest of its budget;
+    the output grid stays counted against the budget until the caller drops
+    its last reference to it (a weak-reference finalizer returns the bytes),
+    so results held by callers bound admission like running jobs do.
 
 Latency = completion time - arrival time.  Results are bit-identical to
 running each job alone with the same plan: the same kernels run on the same
@@ -27,6 +30,7 @@ import concurrent.futures as cf
 import dataclasses
 import threading
 import time
+import weakref
 from typing import Any, Callable, Optional
 
 import numpy as np
@@ -127,8 +131,12 @@ class GpuExecutor:
         return p
 
     def footprint(self, job) -> int:
+        return 2 * self.output_bytes(job) + (1 << 20)
+
+    def output_bytes(self, job) -> int:
+        """Device bytes of the result grid handed to the caller."""
         D = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}[job.dtype]
-        return 2 * int(np.prod(job.dims)) * D + (1 << 20)
+        return int(np.prod(job.dims)) * D
 
     def _stream_index(self, job) -> int:
         if job.d == 2 or len(self.streams) == 1:
@@ -181,6 +189,17 @@ class GpuExecutor:
             events.append(ev)
         return events
 
+    def run_job(self, state, steps):
+        """All `steps` of one job in one stencil_run call on its stream (the
+        one-plan-per-call form); returns an event handle."""
+        torch = self.torch
+        st = self.streams[state["stream"]]
+        state["plan"].run(state["a"], state["b"], steps, stream=st)
+        state["a"], state["b"] = state["b"], state["a"]
+        ev = torch.cuda.Event()
+        ev.record(st)
+        return [ev]
+
     def pass_steps(self, state, left) -> int:
         return min(state["T"], left)
 
@@ -209,7 +228,8 @@ class StencilServer:
                  clock: Callable[[], float] = time.perf_counter):
         self.ex = executor
         self.budget = int(hbm_budget)
-        self.used = 0
+        self.used = 0   # bytes of admitted jobs and of results callers still hold
+        self.held = 0   # of which: results handed back and not yet released
         self.clock = clock
         self.max_inflight = max(1, int(max_inflight_rounds))
         self._queue = collections.deque()
@@ -287,10 +307,25 @@ class StencilServer:
     def _finish(self, a: _Active, now: float):
         out = self.ex.result(a.state)
         self.ex.release(a.state)
-        self.used -= a.bytes
+        held = 0
+        if out is not None and hasattr(self.ex, "output_bytes"):
+            held = min(a.bytes, int(self.ex.output_bytes(a.job)))
+            try:
+                weakref.finalize(out, self._output_dropped, held)
+            except TypeError:  # an output type without weak references is not tracked
+                held = 0
+        self.used -= a.bytes - held
+        self.held += held
         # the server keeps timing records only; the output goes to the caller
         self.done.append(Done(a.job, None, a.arrival, a.admitted, now))
         a.fut.set_result(Done(a.job, out, a.arrival, a.admitted, now))
+
+    def _output_dropped(self, nbytes: int):
+        """Finalizer of a result grid: the caller released it."""
+        with self._cv:
+            self.used -= nbytes
+            self.held -= nbytes
+            self._cv.notify()
 
     def _reap_ready(self):
         """Finish the jobs of every completed round at the head of the queue
@@ -370,7 +405,8 @@ def latency_stats(done):
 
 
 def run_fifo(executor, jobs, clock=time.perf_counter, t0=None, keep_outputs=True):
-    """Baseline: one plan per call, jobs run alone in arrival order, each
+    """Baseline: one plan per call.  Jobs run alone in arrival order, each as
+    a single library call over all its steps (executor.run_job), and each is
     synchronised before the next starts."""
     t0 = clock() if t0 is None else t0
     done = []
@@ -379,14 +415,7 @@ def run_fifo(executor, jobs, clock=time.perf_counter, t0=None, keep_outputs=True
         if job.arrival + t0 > now:
             time.sleep(job.arrival + t0 - now)
         st = executor.prepare(job)
-        left = int(job.steps)
-        h = None
-        while left > 0:
-            s = executor.pass_steps(st, left)
-            h = executor.run_round([st], [s])
-            left -= s
-        if h is not None:
-            executor.wait(h)
+        executor.wait(executor.run_job(st, int(job.steps)))
         fin = clock()
         done.append(Done(job, executor.result(st) if keep_outputs else None, job.arrival + t0,
                          job.arrival + t0, fin))

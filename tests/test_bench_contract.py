@@ -102,3 +102,53 @@ def test_paper_cases_table_is_table3():
         assert (c[1], c[2], c[3], c[4]) == (g["shape"], g["d"], g["r"], g["t"])
         assert c[5] == {"double": "f64", "float": "f32"}[g["dtype"]]
         assert c[6] == (g["cu"]["gst"], g["tc"]["gst"])
+
+
+def _synthetic_sections():
+    variants = {}
+    for shape in ("box", "star"):
+        for dt in ("f64", "f32"):
+            for T in (1, 2, 4):
+                for path in ("valu", "mfma"):
+                    variants[f"{shape}-2d3r-{dt}-T{T}-{path}"] = {
+                        "gst": 1234.5678, "ms_per_sweep": 12.3456, "path": path,
+                        "roofline": {"bound": "alu", "achieved": 33.3333, "peak": 78.6,
+                                     "unit": "TFLOP/s", "frac": 0.4241}}
+    mcheck = {"agree": 36, "total": 36, "cases": [{"case": "x"}] * 36}
+    precision = {"reference": {"gst": 500.0}}
+    for k in ("bf16-mfma-T4", "f16-mfma-T4", "bf16x3-mfma-T4", "bf16-mfma-T2", "bf16-valu-T2",
+              "f16-valu-T2", "f32-valu-T2", "f32-mfma-T4"):
+        precision[k] = {"gst": 2434.123456, "err_every_100": [1e-3] * 10,
+                        "oracle_e2e_1000": 0.0595123456, "oracle_arith_1000": 0.0123456789}
+    lat = {"p50_ms": 5.0345, "p99_ms": 106.0871, "gst": 138.0603}
+    serving = {"served": lat, "fifo": lat, "served_capacity": {"gst": 231.04}, "fifo_capacity": {"gst": 175.9}}
+    cases = {str(i): {"valu": {"gst": 799.43}, "mfma": {"gst": 485.59}, "predicted": "valu",
+                      "measured": "valu"} for i in range(1, 7)}
+    return variants, mcheck, precision, serving, cases
+
+
+def test_json_line_is_small_and_complete():
+    import argparse
+    variants, mcheck, precision, serving, cases = _synthetic_sections()
+    args = argparse.Namespace(steps=20, warmup=5, n=8192, time_steps=100)
+    head_name = "box-2d3r-f64-T2-valu"
+    hv = next(v for v in bench.headline_variants(8192, 100) if v["name"] == head_name)
+    roof = dict(variants[head_name]["roofline"], traffic=1.133e9)
+    cpu = {"value": 0.1153456, "unit": "GStencil/s", "cores": 16, "kind": "oracle",
+           "sample": "Box-2D3R f64 8192x8192, 16 time steps (of 100), zero Dirichlet halo",
+           "cpu_model": "AMD EPYC 9575F 64-Core Processor", "nproc": 256, "affinity": 16}
+    clocks = {"sclk_mhz": 2400, "mclk_mhz": 1900, "fclk_mhz": 2000, "socclk_mhz": 1200}
+    summ = bench.summaries(variants, mcheck, precision, serving, cases)
+    s = bench.compact_line(args, head_name, variants[head_name], hv, roof, cpu, clocks, summ)
+    assert len(s.encode()) <= 4096, len(s)
+    line = json.loads(s)
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline", "clocks"):
+        assert k in line, k
+    assert line["dtype"] == "f64" and line["n_gpus"] == 1 and line["steps"] == 20
+    assert "workload" in line["config"] and "model" not in line["config"]
+    assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
+    assert set(line["cpu_baseline"]) >= {"value", "unit", "cores", "kind", "sample", "cpu_model", "nproc"}
+    assert line["summary"]["model_check"] == "36/36"
+    assert len(line["summary"]["precision"]["bf16-mfma-T4"]) == 3
+    assert line["summary"]["serving"]["served"] == [5.03, 106.09, 138.1]

@@ -99,3 +99,35 @@ def test_batch_argument_errors(stl):
     with pytest.raises(stl.StencilError) as e:
         stl.run_batch([p], [x], [x], [1])
     assert e.value.status == "ALIAS"
+
+
+def test_batch_job_tables_beyond_staging_capacity(stl):
+    """Job tables larger than the staging slot's initial 64 KiB: the slot
+    grows while tables staged earlier in the same call are still to be read
+    (a float64 Box-2D3R job entry carries its 49 weights, so 150 jobs of a
+    variant stage about 70 KiB).  Two variants, two calls in a row; every
+    result equals the job run alone, bit for bit."""
+    import torch
+    w = si.normalised_weights(49, 3)
+    plans, ins, outs, steps = [], [], [], []
+    for k in range(300):
+        dims = (16 + (k % 7), 20 + (k * 13) % 61)
+        T = 1 if k < 150 else 2
+        plans.append(stl.Plan("box", 2, 3, w, dims, T=T, dtype="f64", path="valu"))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(9000 + k)
+        ins.append(torch.rand(dims, generator=g, device="cuda", dtype=torch.float64))
+        outs.append(torch.empty_like(ins[-1]))
+        steps.append(T)
+    ref = []
+    for p, x, s in zip(plans, ins, steps):
+        y = torch.empty_like(x)
+        p.run(x, y, s)
+        ref.append(y)
+    for _ in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        stl.run_batch(plans, ins, outs, steps)
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(ref, outs)):
+            assert torch.equal(a, b), k

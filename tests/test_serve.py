@@ -21,6 +21,7 @@ class FakeExecutor:
         self.lock = threading.Lock()
         self.order = []
         self.device_free_at = 0.0  # rounds execute one after another, like a stream
+        self.whole_jobs = []
 
     def footprint(self, job):
         if job.dims is None:
@@ -48,6 +49,14 @@ class FakeExecutor:
             s["passes"] += 1
         start = max(time.perf_counter(), self.device_free_at)
         self.device_free_at = start + self.pass_time * len(states)
+        return self.device_free_at
+
+    def run_job(self, st, steps):
+        """One call over all of a job's steps (the one-plan-per-call form)."""
+        self.whole_jobs.append((st["job"].id, steps))
+        st["passes"] += -(-steps // self.T)
+        start = max(time.perf_counter(), self.device_free_at)
+        self.device_free_at = start + self.pass_time * (-(-steps // self.T))
         return self.device_free_at
 
     def done(self, h):
@@ -187,4 +196,53 @@ def test_fifo_baseline_runs_jobs_alone():
         j.arrival = 0.001 * i
     done = run_fifo(ex, jobs)
     assert [d.job.id for d in done] == list(range(5))
-    assert all(len(r) == 1 for r in ex.rounds)
+    # one library call per job over all its steps, no rounds
+    assert ex.whole_jobs == [(i, 3) for i in range(5)] and ex.rounds == []
+    assert [d.output for d in done] == [("out", i, 2) for i in range(5)]
+
+
+class Output:
+    """A result grid stand-in that supports weak references."""
+
+    def __init__(self, job_id, passes):
+        self.id, self.passes = job_id, passes
+
+
+class HoldingExecutor(FakeExecutor):
+    """Reports the size of each job's result grid, so the server keeps it
+    counted against the budget until the caller drops it."""
+
+    def output_bytes(self, job):
+        return int(job.dims[0]) // 2
+
+    def result(self, st):
+        return Output(st["job"].id, st["passes"])
+
+
+def test_outputs_held_by_callers_count_against_the_budget():
+    import gc
+
+    ex = HoldingExecutor(pass_time=0.001)
+    srv = StencilServer(ex, hbm_budget=25).start()
+    a = srv.submit(_job("a", size=10, steps=2)).result(timeout=10)
+    b = srv.submit(_job("b", size=10, steps=2)).result(timeout=10)
+    # two outputs of 5 bytes held: 10 of 25 used, a job of footprint 10 fits ...
+    assert srv.used == 10 and srv.held == 10
+    c = srv.submit(_job("c", size=10, steps=2)).result(timeout=10)
+    assert srv.used == 15
+    # ... but not one of footprint 16: admission blocks while the outputs are held
+    blocked = srv.submit(_job("d", size=16, steps=2))
+    time.sleep(0.1)
+    assert not blocked.done() and "d" not in ex.order
+    del a
+    gc.collect()
+    time.sleep(0.1)
+    assert not blocked.done()  # 15 - 5 = 10 used: 10 + 16 > 25 still
+    del b
+    gc.collect()
+    d = blocked.result(timeout=10)
+    assert d.output.id == "d" and srv.used == 5 + 8
+    del c, d, blocked  # the future holds the result too
+    gc.collect()
+    srv.stop()
+    assert srv.used == 0 and srv.held == 0
