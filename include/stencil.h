@@ -165,6 +165,27 @@ int stencil_run_batch(int n, const stencil_plan_t *plans, const void *const *ins
 int stencil_plan_autotune(stencil_plan_t plan, const void *in, void *out, int64_t steps,
                           int max_candidates, void *stream, double *best_gst);
 
+/* Size of the static device array stencil_run_noalloc uses (64 MiB). */
+#define STENCIL_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as stencil_run, with the same kernels, but the intermediate grid of
+ * a run of two or more passes lives in a static device array of
+ * STENCIL_NOALLOC_SCRATCH_BYTES held by each GPU the library runs on until the
+ * process ends, and the call allocates nothing.  The caller passes `in` and
+ * `out` as for stencil_run.  Every call on one GPU shares that GPU's array,
+ * so calls that overlap on one GPU (other streams, other threads) race; the
+ * array needs no clearing between calls.
+ * Errors: INVALID_ARG (NULL pointers, steps < 0, or a run of two or more
+ * passes over a grid larger than STENCIL_NOALLOC_SCRATCH_BYTES), ALIAS,
+ * UNSUPPORTED (an MFMA plan whose operand fragments are not yet on the
+ * current device: run it once with stencil_run there first, which uploads
+ * them), HIP.
+ */
+int stencil_run_noalloc(stencil_plan_t plan, const void *in, void *out, int64_t steps, void *stream);
+
 /* Release a plan and its device memory.  Call only after the stream that ran
  * it has drained.  NULL is ignored. */
 void stencil_plan_destroy(stencil_plan_t plan);

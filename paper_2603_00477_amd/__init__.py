@@ -94,6 +94,16 @@ class Plan:
                                 _stream_handle(stream)), "stencil_run")
         return out
 
+    def run_noalloc(self, inp, out, steps, stream=None):
+        """stencil_run_noalloc: as run(), with the intermediate grid in the
+        library's static device array (no device allocation)."""
+        self._check_tensor(inp, "in")
+        self._check_tensor(out, "out")
+        check(lib().stencil_run_noalloc(self._h, ctypes.c_void_p(inp.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), int(steps),
+                                        _stream_handle(stream)), "stencil_run_noalloc")
+        return out
+
     def autotune(self, inp, out, steps, max_candidates=4, stream=None) -> float:
         """Choose path, T and tile rows by timing model-ranked candidates on
         inp -> out (out is overwritten).  Returns the measured GStencil/s."""

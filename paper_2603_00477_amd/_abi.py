@@ -21,7 +21,9 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALIAS", 4: "OOM", 5: 
 SYMBOLS = ["stencil_plan", "stencil_plan_set", "stencil_plan_info", "stencil_run",
            "stencil_run_batch", "stencil_plan_destroy", "stencil_last_error", "stencil_compose",
            "stencil_hw_default", "stencil_model_predict", "stencil_mfma_sparsity",
-           "stencil_plan_autotune", "stencil_microbench", "stencil_kernel_available"]
+           "stencil_plan_autotune", "stencil_microbench", "stencil_kernel_available",
+           "stencil_run_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20  # STENCIL_NOALLOC_SCRATCH_BYTES
 
 
 class PlanInfo(ctypes.Structure):
@@ -76,6 +78,7 @@ def lib():
     L.stencil_plan_set.argtypes = [vp, ctypes.c_int, ctypes.c_double]
     L.stencil_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.stencil_run.argtypes = [vp, vp, vp, i64, vp]
+    L.stencil_run_noalloc.argtypes = [vp, vp, vp, i64, vp]
     L.stencil_run_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(vp), i64p, vp]
     L.stencil_plan_destroy.argtypes = [vp]
@@ -94,7 +97,7 @@ def lib():
     L.stencil_kernel_available.argtypes = [ctypes.c_int] * 6
     L.stencil_kernel_available.restype = ctypes.c_int
     for name in ("stencil_plan", "stencil_plan_set", "stencil_plan_info", "stencil_run",
-                 "stencil_plan_autotune",
+                 "stencil_plan_autotune", "stencil_run_noalloc",
                  "stencil_run_batch", "stencil_compose", "stencil_hw_default",
                  "stencil_model_predict"):
         getattr(L, name).restype = ctypes.c_int

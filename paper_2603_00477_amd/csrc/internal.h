@@ -134,6 +134,12 @@ void mfma_build_fragments(int shape, int d, int r, const double *w, int steps, i
 
 int device_cu_count();
 
+// stencil_run with a caller-provided intermediate grid (`scratch`, capacity
+// `scratch_cap` bytes): no device memory is allocated.  MFMA plans must
+// already hold their operand fragments on the current device.
+int run_without_allocation(struct ::stencil_plan_s *p, const void *in, void *out, int64_t steps,
+                           hipStream_t stream, void *scratch, size_t scratch_cap);
+
 }  // namespace stl
 
 struct stencil_plan_s {

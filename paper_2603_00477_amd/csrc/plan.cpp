@@ -392,7 +392,10 @@ hipError_t launch_fixup(const stencil_plan_s *p, int t, const void *src, void *d
     return hipSuccess;
 }
 
-int run_one(stencil_plan_s *p, const void *in, void *out, int64_t steps, hipStream_t stream)
+// `scratch` holds the intermediate grid of multi-pass runs (at least one
+// grid of the plan's dims and dtype when the schedule has two or more passes).
+int run_one(stencil_plan_s *p, const void *in, void *out, int64_t steps, hipStream_t stream,
+            void *scratch)
 {
     const size_t bytes = grid_bytes(p);
     if (steps == 0) {
@@ -404,7 +407,7 @@ int run_one(stencil_plan_s *p, const void *in, void *out, int64_t steps, hipStre
     const int P = (int)passes.size();
     const void *src = in;
     for (int i = 0; i < P; ++i) {
-        void *dst = ((P - 1 - i) % 2 == 0) ? out : p->scratch;
+        void *dst = ((P - 1 - i) % 2 == 0) ? out : scratch;
         const PassDesc &pd = passes[i];
         if (!pd.k) return fail(STENCIL_ERR_UNSUPPORTED, "no kernel for a pass");
         PassArgs a = base_args(p, pd.t);
@@ -504,6 +507,37 @@ bool overlap(const void *a, const void *b, size_t n)
 }
 
 }  // namespace
+
+namespace stl {
+
+int run_without_allocation(stencil_plan_s *p, const void *in, void *out, int64_t steps,
+                           hipStream_t stream, void *scratch, size_t scratch_cap)
+{
+    if (!p || !in || !out) return fail(STENCIL_ERR_INVALID_ARG, "stencil_run_noalloc: NULL plan or buffer");
+    if (steps < 0) return fail(STENCIL_ERR_INVALID_ARG, "stencil_run_noalloc: steps < 0");
+    const size_t bytes = grid_bytes(p);
+    if (overlap(in, out, bytes)) return fail(STENCIL_ERR_ALIAS, "stencil_run_noalloc: in and out overlap");
+    const bool multi = steps > 0 && schedule(p, steps).size() > 1;
+    if (multi && bytes > scratch_cap)
+        return fail(STENCIL_ERR_INVALID_ARG,
+                    "stencil_run_noalloc: the grid (" + std::to_string(bytes) +
+                        " bytes) exceeds the static scratch of " + std::to_string(scratch_cap) +
+                        " bytes that a run of two or more passes needs");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (p->device != dev) {
+        // only the MFMA operand fragments would need device memory
+        if (p->path == STENCIL_PATH_MFMA)
+            return fail(STENCIL_ERR_UNSUPPORTED,
+                        "stencil_run_noalloc: this MFMA plan has no operand fragments on the current "
+                        "device; run it once with stencil_run there first (that call uploads them)");
+        p->device = dev;
+    }
+    return run_one(p, in, out, steps, stream, scratch);
+}
+
+}  // namespace stl
 
 extern "C" const char *stencil_last_error(void) { return g_last_error.c_str(); }
 
@@ -673,7 +707,7 @@ extern "C" int stencil_run(stencil_plan_t p, const void *in, void *out, int64_t 
     if (overlap(in, out, grid_bytes(p))) return fail(STENCIL_ERR_ALIAS, "stencil_run: in and out overlap");
     int rc = ensure_device(p, steps > 0 && schedule(p, steps).size() > 1);
     if (rc) return rc;
-    return run_one(p, in, out, steps, (hipStream_t)stream);
+    return run_one(p, in, out, steps, (hipStream_t)stream, p->scratch);
 }
 
 extern "C" int stencil_run_batch(int n, const stencil_plan_t *plans, const void *const *ins,
