@@ -96,6 +96,13 @@ typedef struct {
     double predicted_gst_mfma;
     int predicted_winner;       /* -1 VALU, 0 tie, +1 MFMA                    */
     int scenario;               /* 1..4 as in the paper's four scenarios      */
+    int tile_rows;              /* VALU rows (planes) streamed per workgroup,
+                                   0 = chosen per launch                     */
+    int T_fused;                /* steps one launch fuses in a full pass: T,
+                                   or 1 where no kernel fuses T steps of this
+                                   pattern and a pass runs as T one-step
+                                   launches (same result, T times the
+                                   traffic)                                   */
 } stencil_plan_info_t;
 
 /*

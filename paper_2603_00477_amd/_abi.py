@@ -34,7 +34,7 @@ class PlanInfo(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("halo", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_int64), ("predicted_gst_valu", ctypes.c_double),
                 ("predicted_gst_mfma", ctypes.c_double), ("predicted_winner", ctypes.c_int),
-                ("scenario", ctypes.c_int)]
+                ("scenario", ctypes.c_int), ("tile_rows", ctypes.c_int), ("T_fused", ctypes.c_int)]
 
 
 class HW(ctypes.Structure):

@@ -36,6 +36,8 @@ VARIANTS_2D = [(s, 3, T, dt, path) for s in ("box", "star") for dt in ("f64", "f
 VARIANTS_3D = [(s, r, T, dt, path) for s, r in (("star", 2), ("box", 1)) for dt in ("f64", "f32")
                for T in (1, 2, 3) for path in ("valu", "mfma")]
 VARIANTS_16 = [("box", 2, T, dt, "mfma") for dt in ("bf16", "f16", "bf16x3") for T in (1, 2, 4)]
+# the 8192^2 vector-unit variants of the benchmark's first workload
+VARIANTS_HEAD = [(s, 3, T, dt, "valu") for s in ("box", "star") for dt in ("f64", "f32") for T in (1, 2, 4)]
 # arithmetic intensity against fusion depth on the vector units (paper,
 # Sec. "Arithmetic Intensity Analysis": Box-2D1R and Star-2D1R, double)
 VARIANTS_AI_T = [(s, 1, T, "f64", "valu") for s in ("box", "star") for T in range(1, 9)]
@@ -54,6 +56,10 @@ def run(n2: int, n3: int, which: str = "model"):
         todo = [(2, v) for v in VARIANTS_AI_T]
     elif which == "p16":
         todo = [(2, v) for v in VARIANTS_16]
+    elif which == "head":
+        todo = [(2, v) for v in VARIANTS_HEAD]
+    elif which == "v3":
+        todo = [(3, v) for v in VARIANTS_3D if v[4] == "valu"]
     else:
         todo = [(2, v) for v in VARIANTS_2D] + [(3, v) for v in VARIANTS_3D] + [(2, v) for v in VARIANTS_16]
     x_cache = {}
@@ -153,9 +159,10 @@ def main(argv=None):
     r = sub.add_parser("run")
     r.add_argument("--n2", type=int, default=4096)
     r.add_argument("--n3", type=int, default=256)
-    r.add_argument("--set", default="model", choices=["model", "ai_t", "p16"],
+    r.add_argument("--set", default="model", choices=["model", "ai_t", "p16", "head", "v3"],
                    help="model: every 8192^2 / 512^3 / precision variant; ai_t: Box/Star-2D1R "
-                        "float64 at T = 1..8; p16: the 16-bit and compensated MFMA variants only")
+                        "float64 at T = 1..8; p16: the 16-bit and compensated MFMA variants only; "
+                        "head: the 2D VALU variants of the first workload; v3: the 3D VALU variants")
     rep = sub.add_parser("report")
     rep.add_argument("fetch")
     rep.add_argument("write")

@@ -81,6 +81,12 @@ private:
     int cur_ = kSlots - 1;
 };
 
+// Stage a batched launch's job table (`job_bytes` bytes) and the tile-start
+// prefix of its jobs as one block; *djobs and *dstart receive the device
+// addresses of the two parts.
+hipError_t stage_job_table(BatchStaging *stage, const void *jobs, size_t job_bytes,
+                           const std::vector<int> &start, void **djobs, void **dstart, hipStream_t stream);
+
 // One launchable kernel variant.
 struct KernelEntry {
     int path;    // STENCIL_PATH_VALU or STENCIL_PATH_MFMA

@@ -191,8 +191,9 @@ struct BandCols {
     static constexpr int PF = PF0 < 2 ? 2 : (PF0 > N ? N : PF0);
 };
 
+// One 16V x 16NW output tile of one pass, run by the whole workgroup.
 template <int DT, int SHAPE, int r, int T, int V, int NW>
-__global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
+__device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
 {
     using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
     using MT = typename Cfg::MT;
@@ -217,8 +218,6 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
     __shared__ __attribute__((aligned(16))) FRS lA[ALDS ? NAF * 64 : 1];
 
     const int tid = threadIdx.x;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= a.ntiles) return;
     const int tr = tile / a.ntc, tcn = tile - tr * a.ntc;
     const int r0 = tr * Cfg::TR, c0 = tcn * Cfg::TCOL;
     const int n0 = a.n0, n1 = a.n1;
@@ -521,18 +520,50 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
     }
 }
 
-template <int DT, int SHAPE, int r, int T>
-hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
+template <int DT, int SHAPE, int r, int T, int V, int NW>
+__global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 {
-    // 16-bit storage with composite radius >= 6: eight waves side by side
-    // (64 x 128 workgroup tiles, a smaller halo share) measured 5-18 % faster
-    // on 16384^2; smaller radii and the compensated mode keep four (up to 12 %
-    // slower with eight)
-    constexpr int V = 4, NW = (MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3 && r * T >= 6) ? 8 : 4;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    mfma2d_tile<DT, SHAPE, r, T, V, NW>(a, tile);
+}
+
+// Persistent batched launch over the tiles of several jobs: workgroup b takes
+// items b + i*gridDim of one list; tile_start[j] is the first item of job j
+// (tile_start[njobs] = total).  A barrier between items keeps the next
+// item's staging from overwriting LDS blocks still being read.
+template <int DT, int SHAPE, int r, int T, int V, int NW>
+__global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs *__restrict__ jobs,
+                                                             const int *__restrict__ tile_start, int njobs)
+{
+    const int total = tile_start[njobs];
+    int j = 0;
+    for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
+        while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
+        const Mfma2DArgs a = jobs[j];
+        mfma2d_tile<DT, SHAPE, r, T, V, NW>(a, item - tile_start[j]);
+        __syncthreads();
+    }
+}
+
+// 16-bit storage with composite radius >= 6: eight waves side by side (64 x
+// 128 workgroup tiles, a smaller halo share) measured 5-18 % faster on
+// 16384^2; smaller radii and the compensated mode keep four (up to 12 %
+// slower with eight).
+template <int DT, int r, int T>
+struct Mfma2DShape {
+    static constexpr int V = 4;
+    static constexpr int NW = (MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3 && r * T >= 6) ? 8 : 4;
+};
+
+template <int DT, int SHAPE, int r, int T>
+bool mfma2d_args(const PassArgs &p, Mfma2DArgs *out)
+{
+    constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
     using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
-    if (p.steps != T || !p.afrag) return hipErrorInvalidValue;
-    if (MfmaTypes<DT>::X3 && !p.afrag_lo) return hipErrorInvalidValue;
-    Mfma2DArgs a;
+    if (p.steps != T || !p.afrag) return false;
+    if (MfmaTypes<DT>::X3 && !p.afrag_lo) return false;
+    Mfma2DArgs &a = *out;
     a.src = p.src;
     a.dst = p.dst;
     a.afrag = p.afrag;
@@ -544,12 +575,56 @@ hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
     a.ntr = (a.n0 + Cfg::TR - 1) / Cfg::TR;
     a.ntc = (a.n1 + Cfg::TCOL - 1) / Cfg::TCOL;
     a.ntiles = a.ntr * a.ntc;
+    return true;
+}
+
+template <int DT, int SHAPE, int r, int T>
+hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
+{
+    constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
+    Mfma2DArgs a;
+    if (!mfma2d_args<DT, SHAPE, r, T>(p, &a)) return hipErrorInvalidValue;
+    if (a.ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW>), dim3(a.ntiles), dim3(64 * NW), 0,
                        stream, a);
     return hipGetLastError();
 }
 
-#define M2(DT, SH, R, T) {STENCIL_PATH_MFMA, DT, SH, 2, R, T, &launch_mfma2d<DT, SH, R, T>, nullptr}
+// n passes (one per job) of this variant in one persistent launch.
+template <int DT, int SHAPE, int r, int T>
+hipError_t launch_mfma2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
+{
+    constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
+    std::vector<Mfma2DArgs> jobs;
+    std::vector<int> start(1, 0);
+    jobs.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        Mfma2DArgs a;
+        if (!mfma2d_args<DT, SHAPE, r, T>(ps[i], &a)) return hipErrorInvalidValue;
+        if (a.ntiles <= 0) continue;
+        if ((int64_t)start.back() + a.ntiles > (1LL << 30)) return hipErrorInvalidValue;
+        jobs.push_back(a);
+        start.push_back(start.back() + a.ntiles);
+    }
+    if (jobs.empty()) return hipSuccess;
+    void *djobs = nullptr, *dstart = nullptr;
+    hipError_t e = stage_job_table(stage, jobs.data(), jobs.size() * sizeof(Mfma2DArgs), start, &djobs,
+                                   &dstart, stream);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, mfma2d_batch_kernel<DT, SHAPE, r, T, V, NW>,
+                                                     64 * NW, 0);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    const int slots = occ * (ps[0].num_cu > 0 ? ps[0].num_cu : 256);
+    const int total = start.back();
+    hipLaunchKernelGGL((mfma2d_batch_kernel<DT, SHAPE, r, T, V, NW>), dim3(total < slots ? total : slots),
+                       dim3(64 * NW), 0, stream, static_cast<const Mfma2DArgs *>(djobs),
+                       static_cast<const int *>(dstart), (int)jobs.size());
+    return hipGetLastError();
+}
+
+#define M2(DT, SH, R, T) \
+    {STENCIL_PATH_MFMA, DT, SH, 2, R, T, &launch_mfma2d<DT, SH, R, T>, &launch_mfma2d_batch<DT, SH, R, T>}
 #define M2_T(DT, SH, R) M2(DT, SH, R, 1), M2(DT, SH, R, 2), M2(DT, SH, R, 3), M2(DT, SH, R, 4)
 #define M2_R(DT, SH) M2_T(DT, SH, 1), M2_T(DT, SH, 2), M2_T(DT, SH, 3)
 #define M2_S(DT) M2_R(DT, STENCIL_STAR), M2_R(DT, STENCIL_BOX)

@@ -427,8 +427,9 @@ int run_one(stencil_plan_s *p, const void *in, void *out, int64_t steps, hipStre
 
 // Batched runs: round j issues pass j of every job that has one.  Passes of
 // one round that share a kernel variant go out as one persistent batched
-// launch (workgroups pull tiles of all those grids from one list); the rest
-// (MFMA passes, Dirichlet fix-ups) are launched one by one.  Each job's
+// launch (workgroups pull tiles of all those grids from one list); variants
+// without a batched form go out one by one, and the Dirichlet band fix-ups
+// of kernel-fused MFMA passes follow the round's launches.  Each job's
 // passes stay in stream order and ping-pong exactly as in run_one, so every
 // result is bit-identical to running the job alone.
 std::mutex g_batch_mu;
@@ -463,8 +464,15 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
         rounds = std::max(rounds, sched[i].size());
     }
     std::vector<const void *> src(ins, ins + n);
+    struct Fixup {
+        stencil_plan_s *p;
+        int t;
+        const void *src;
+        void *dst;
+    };
     for (size_t j = 0; j < rounds; ++j) {
         std::map<const KernelEntry *, std::vector<PassArgs>> groups;
+        std::vector<Fixup> fixups;  // Dirichlet bands, after the passes they correct
         for (int i = 0; i < n; ++i) {
             const auto &ps = sched[i];
             if (j >= ps.size()) continue;
@@ -477,16 +485,16 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
             a.src = src[i];
             a.dst = dst;
             src[i] = dst;
-            if (pd.k->launch_batch && !pd.fixup && pd.path == STENCIL_PATH_VALU) {
-                groups[pd.k].push_back(a);
-                continue;
-            }
             if (pd.path == STENCIL_PATH_MFMA) {
                 a.afrag = p->afrag[pd.t];
                 a.afrag_lo = p->afrag_lo[pd.t];
             }
+            if (pd.fixup) fixups.push_back({p, pd.t, a.src, dst});
+            if (pd.k->launch_batch) {
+                groups[pd.k].push_back(a);
+                continue;
+            }
             e = pd.k->launch(a, stream);
-            if (e == hipSuccess && pd.fixup) e = launch_fixup(p, pd.t, a.src, dst, stream);
             if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
         }
         for (auto &g : groups) {
@@ -495,6 +503,10 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
             e = v.size() == 1 ? k->launch(v[0], stream)
                               : k->launch_batch(v.data(), (int)v.size(), &stage, stream);
             if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("batched launch: ") + hipGetErrorString(e));
+        }
+        for (const Fixup &f : fixups) {
+            e = launch_fixup(f.p, f.t, f.src, f.dst, stream);
+            if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
         }
     }
     return STENCIL_OK;
@@ -696,6 +708,11 @@ extern "C" int stencil_plan_info(stencil_plan_t p, stencil_plan_info_t *out)
     i.predicted_gst_mfma = p->pred_mfma;
     i.predicted_winner = p->pred_winner;
     i.scenario = p->scenario;
+    i.tile_rows = p->tile_rows;
+    const bool fused = find_kernel(p->path, p->dtype, p->shape, p->d, p->r, p->T) != nullptr ||
+                       (p->path == STENCIL_PATH_MFMA &&
+                        find_kernel(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T) != nullptr);
+    i.T_fused = fused ? p->T : 1;
     *out = i;
     return STENCIL_OK;
 }

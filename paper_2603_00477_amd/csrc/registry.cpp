@@ -97,6 +97,21 @@ BatchStaging::~BatchStaging()
 }
 
 
+hipError_t stage_job_table(BatchStaging *stage, const void *jobs, size_t job_bytes,
+                           const std::vector<int> &start, void **djobs, void **dstart, hipStream_t stream)
+{
+    const size_t jb = (job_bytes + 255) & ~(size_t)255;
+    std::vector<uint8_t> blob(jb + start.size() * sizeof(int));
+    std::memcpy(blob.data(), jobs, job_bytes);
+    std::memcpy(blob.data() + jb, start.data(), start.size() * sizeof(int));
+    void *d = nullptr;
+    hipError_t e = stage->put(blob.data(), blob.size(), &d, stream);
+    if (e != hipSuccess) return e;
+    *djobs = d;
+    *dstart = static_cast<uint8_t *>(d) + jb;
+    return hipSuccess;
+}
+
 std::vector<const std::vector<KernelEntry> *> all_kernel_tables()
 {
     return {&valu2d_table_f64(),   &valu2d_table_f32(),  &valu2d_table_bf16(), &valu2d_table_f16(),

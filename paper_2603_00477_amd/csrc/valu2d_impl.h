@@ -31,7 +31,6 @@
 #pragma once
 
 #include <cstddef>
-#include <cstring>
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
@@ -555,16 +554,9 @@ hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
     }
     if (jobs.empty()) return hipSuccess;
     const int nj = (int)jobs.size();
-    // job table and tile starts travel as one staged block
-    const size_t jbytes = (jobs.size() * sizeof(Job) + 255) & ~(size_t)255;
-    std::vector<uint8_t> blob(jbytes + start.size() * sizeof(int));
-    std::memcpy(blob.data(), jobs.data(), jobs.size() * sizeof(Job));
-    std::memcpy(blob.data() + jbytes, start.data(), start.size() * sizeof(int));
-    void *dblob = nullptr;
-    hipError_t e = stage->put(blob.data(), blob.size(), &dblob, stream);
+    void *djobs = nullptr, *dstart = nullptr;
+    hipError_t e = stage_job_table(stage, jobs.data(), jobs.size() * sizeof(Job), start, &djobs, &dstart, stream);
     if (e != hipSuccess) return e;
-    void *djobs = dblob;
-    void *dstart = static_cast<uint8_t *>(dblob) + jbytes;
     const int total_wg = start.back();
     int occ = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(

@@ -80,9 +80,12 @@ __device__ __forceinline__ int star3_index(int axis, int off)
     return 1 + axis * 2 * R + (off < 0 ? off + R : off + R - 1);
 }
 
+// One tile (in-plane tile x plane segment) of one pass, run by the whole
+// workgroup; `lds` holds T double-buffered planes.
 template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void valu3d_kernel(
-    Valu3DArgs<TC, Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> a)
+__device__ __forceinline__ void valu3d_tile(
+    const Valu3DArgs<TC, Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> &a, const int tile,
+    TC (&lds)[T][2][Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::PLANE])
 {
     using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
     constexpr int K = Cfg::K;
@@ -95,12 +98,8 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
     constexpr int WMODE = Cfg::WMODE;
     using Vec = RawVec<TS, W>;
 
-    __shared__ TC lds[T][2][PLANE];
-
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= a.ntiles) return;
     const int tzs = tile / (a.nty * a.ntx);
     const int rem = tile - tzs * (a.nty * a.ntx);
     const int tyi = rem / a.ntx, txi = rem - tyi * a.ntx;
@@ -368,10 +367,45 @@ __global__ __launch_bounds__(TX *TY) void valu3d_kernel(
 }
 
 template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
-hipError_t launch_valu3d_cfg(const PassArgs &p, hipStream_t stream)
+__global__ __launch_bounds__(TX *TY) void valu3d_kernel(
+    Valu3DArgs<TC, Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> a)
 {
     using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
-    Valu3DArgs<TC, Cfg::K> a;
+    __shared__ TC lds[T][2][Cfg::PLANE];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    valu3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY>(a, tile, lds);
+}
+
+// Persistent batched launch: the workgroups walk one list of tiles spanning
+// every job of the batch; workgroup b takes items b + i*gridDim.  tile_start[j]
+// is the first item of job j (tile_start[njobs] = total).  The tile body ends
+// with a barrier, so the LDS planes are free when the next item starts.
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void valu3d_batch_kernel(
+    const Valu3DArgs<TC, Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> *__restrict__ jobs,
+    const int *__restrict__ tile_start, int njobs)
+{
+    using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    __shared__ TC lds[T][2][Cfg::PLANE];
+    const int total = tile_start[njobs];
+    int j = 0;
+    for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
+        while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
+        const Valu3DArgs<TC, Cfg::K> a = jobs[j];
+        valu3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY>(a, item - tile_start[j], lds);
+    }
+}
+
+// Fill the arguments of one pass; returns false when there is nothing to do
+// (err then says whether the pass is invalid).
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+bool valu3d_args(const PassArgs &p, Valu3DArgs<TC, Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> *out,
+                 hipError_t *err)
+{
+    using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    *err = hipSuccess;
+    Valu3DArgs<TC, Cfg::K> &a = *out;
     a.src = p.src;
     a.dst = p.dst;
     a.n0 = (int)p.dims[0];
@@ -388,9 +422,12 @@ hipError_t launch_valu3d_cfg(const PassArgs &p, hipStream_t stream)
     for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
     a.BYv = Cfg::PY - 2 * Cfg::EY;
     a.BXv = Cfg::PX - 2 * Cfg::EX;
-    if (a.BYv <= 0 || a.BXv <= 0) return hipErrorInvalidValue;
+    if (a.BYv <= 0 || a.BXv <= 0) {
+        *err = hipErrorInvalidValue;
+        return false;
+    }
     const int D0 = a.oz1 - a.oz0, D1 = a.oy1 - a.oy0, D2 = a.ox1 - a.ox0;
-    if (D0 <= 0 || D1 <= 0 || D2 <= 0) return hipSuccess;
+    if (D0 <= 0 || D1 <= 0 || D2 <= 0) return false;
     a.nty = (D1 + a.BYv - 1) / a.BYv;
     a.ntx = (D2 + a.BXv - 1) / a.BXv;
     int BZ = p.tile_rows;
@@ -405,37 +442,95 @@ hipError_t launch_valu3d_cfg(const PassArgs &p, hipStream_t stream)
     a.BZ = BZ;
     a.nzs = (D0 + BZ - 1) / BZ;
     const int64_t nt = (int64_t)a.nzs * a.nty * a.ntx;
-    if (nt > (1LL << 30)) return hipErrorInvalidValue;
+    if (nt > (1LL << 30)) {
+        *err = hipErrorInvalidValue;
+        return false;
+    }
     a.ntiles = (int)nt;
+    return true;
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+hipError_t launch_valu3d_cfg(const PassArgs &p, hipStream_t stream)
+{
+    using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    Valu3DArgs<TC, Cfg::K> a;
+    hipError_t err;
+    if (!valu3d_args<TS, TC, SHAPE, R, T, W, WY, TX, TY>(p, &a, &err)) return err;
     hipLaunchKernelGGL((valu3d_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>), dim3(a.ntiles),
                        dim3(TX * TY), 0, stream, a);
     return hipGetLastError();
 }
 
+// n passes (one per job) of this variant in one persistent launch.
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
+hipError_t launch_valu3d_batch_cfg(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
+{
+    using Cfg = Valu3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    using Args = Valu3DArgs<TC, Cfg::K>;
+    std::vector<Args> jobs;
+    std::vector<int> start(1, 0);
+    jobs.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        Args a;
+        hipError_t err;
+        if (!valu3d_args<TS, TC, SHAPE, R, T, W, WY, TX, TY>(ps[i], &a, &err)) {
+            if (err != hipSuccess) return err;
+            continue;
+        }
+        if ((int64_t)start.back() + a.ntiles > (1LL << 30)) return hipErrorInvalidValue;
+        jobs.push_back(a);
+        start.push_back(start.back() + a.ntiles);
+    }
+    if (jobs.empty()) return hipSuccess;
+    void *djobs = nullptr, *dstart = nullptr;
+    hipError_t e = stage_job_table(stage, jobs.data(), jobs.size() * sizeof(Args), start, &djobs, &dstart,
+                                   stream);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, valu3d_batch_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>, TX * TY, 0);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    const int slots = occ * (ps[0].num_cu > 0 ? ps[0].num_cu : 256);
+    const int total = start.back();
+    hipLaunchKernelGGL((valu3d_batch_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>),
+                       dim3(total < slots ? total : slots), dim3(TX * TY), 0, stream,
+                       static_cast<const Args *>(djobs), static_cast<const int *>(dstart), (int)jobs.size());
+    return hipGetLastError();
+}
+
 // Tile shapes: 16 x 16 threads (32 x 8 for one step per pass); float64 2 x 2
 // points per thread, float32 2 x 4, 16-bit storage 2 x 8.
+//   one step per pass, r <= 2: 32 x 8 threads (wide rows: 64 float64 / 128
+//   float32 columns per tile), measured 14-18 % faster than 16 x 16 on 512^3;
+//   r = 3 (Star-3D3R float32: 371 vs 294 GSt/s) and fused passes keep 16 x 16;
+//   deep composite halos (r T >= 6): 4 rows per thread spilled to AGPRs;
+//   measured on 512^3, Star-3D2R T = 3 runs best with 1 row x 32 thread rows
+//   (+26-36 %), Star-3D3R T = 2 with 2 rows x 16 (+25 %).
+template <typename TS, int R, int T>
+struct Valu3DShape {
+    static constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
+    static constexpr int WY = (T == 1 && R <= 2) ? 2 : (R * T >= 6 ? (R >= 3 ? 2 : 1) : 2);
+    static constexpr int TX = (T == 1 && R <= 2) ? 32 : 16;
+    static constexpr int TY = (T == 1 && R <= 2) ? 8 : (R * T >= 6 ? 32 / WY : 16);
+};
+
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu3d(const PassArgs &p, hipStream_t stream)
 {
-    constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
-    // one step per pass, r <= 2: 32 x 8 threads (wide rows: 64 float64 / 128
-    // float32 columns per tile), measured 14-18 % faster than 16 x 16 on 512^3;
-    // r = 3 (Star-3D3R float32: 371 vs 294 GSt/s) and fused passes keep 16 x 16
-    if constexpr (T == 1 && R <= 2) {
-        return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, 2, 32, 8>(p, stream);
-    } else if constexpr (R * T >= 6) {
-        // deep composite halos: 4 rows per thread spilled to AGPRs; measured on
-        // 512^3, Star-3D2R T = 3 runs best with 1 row x 32 thread rows (+26-36 %),
-        // Star-3D3R T = 2 with 2 rows x 16 (+25 %)
-        constexpr int WY = R >= 3 ? 2 : 1;
-        return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, WY, 16, 32 / WY>(p, stream);
-    } else {
-        return launch_valu3d_cfg<TS, TC, SHAPE, R, T, W, 2, 16, 16>(p, stream);
-    }
+    using S = Valu3DShape<TS, R, T>;
+    return launch_valu3d_cfg<TS, TC, SHAPE, R, T, S::W, S::WY, S::TX, S::TY>(p, stream);
+}
+
+template <typename TS, typename TC, int SHAPE, int R, int T>
+hipError_t launch_valu3d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
+{
+    using S = Valu3DShape<TS, R, T>;
+    return launch_valu3d_batch_cfg<TS, TC, SHAPE, R, T, S::W, S::WY, S::TX, S::TY>(ps, n, stage, stream);
 }
 
 #define V3(TS, TC, DT, SH, R, T) \
-    {STENCIL_PATH_VALU, DT, SH, 3, R, T, &launch_valu3d<TS, TC, SH, R, T>, nullptr}
+    {STENCIL_PATH_VALU, DT, SH, 3, R, T, &launch_valu3d<TS, TC, SH, R, T>, &launch_valu3d_batch<TS, TC, SH, R, T>}
 #define V3_T(TS, TC, DT, SH, R) V3(TS, TC, DT, SH, R, 1), V3(TS, TC, DT, SH, R, 2), V3(TS, TC, DT, SH, R, 3)
 // Instantiated (shape, r, T): those that fit the register file without
 // spilling; other combinations run as single-step passes of the direct kernel.

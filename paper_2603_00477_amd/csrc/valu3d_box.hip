@@ -30,6 +30,7 @@
 // ascending), as in the oracle.
 
 #include <cstddef>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -68,21 +69,24 @@ struct Box3Cfg {
     static constexpr int WINV = (WIN + VE - 1) / VE;     // 16-byte reads per window row
 };
 
+// Weights in the constant address space: loads through it are scalar.
+template <typename TC>
+using WPtr = const __attribute__((address_space(4))) TC *;
+
+// One tile (in-plane tile x plane segment) of one pass, run by the whole
+// workgroup; `wk` points to the K weights of the pass.
 template <typename TS, typename TC, int R, int W, int WY, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
-    Box3Args<TC, Box3Cfg<TS, TC, R, W, WY, TX, TY>::K> a)
+__device__ __forceinline__ void box3_tile(const Box3Args<TC, Box3Cfg<TS, TC, R, W, WY, TX, TY>::K> &a,
+                                          WPtr<TC> wk, const int tile,
+                                          TC (&lds)[2][Box3Cfg<TS, TC, R, W, WY, TX, TY>::PLANE +
+                                                       Box3Cfg<TS, TC, R, W, WY, TX, TY>::VE])
 {
     using Cfg = Box3Cfg<TS, TC, R, W, WY, TX, TY>;
-    using Args = Box3Args<TC, Cfg::K>;
     constexpr int Q = Cfg::Q, NT = Cfg::NT, LX = Cfg::LX, LDX = Cfg::LDX, NPF = Cfg::NPF;
     constexpr int VE = Cfg::VE, WINV = Cfg::WINV;
 
-    __shared__ __align__(16) TC lds[2][Cfg::PLANE + VE];  // + VE: pad slot of the staging
-
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= a.ntiles) return;
     const int tzs = tile / (a.nty * a.ntx);
     const int rem = tile - tzs * (a.nty * a.ntx);
     const int tyi = rem / a.ntx, txi = rem - tyi * a.ntx;
@@ -98,8 +102,6 @@ __global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
     using GPtr = const __attribute__((address_space(1))) TS *;
     const GPtr src = (GPtr)a.src;
     TS *dst = static_cast<TS *>(a.dst);
-    const TC *wk =
-        (const TC *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Args, w));
 
     // staging: element e = tid + p*NT of the LY x LX block.  Its in-plane
     // source offset (clamped to 0 where a Dirichlet grid has no point; bit p
@@ -258,12 +260,52 @@ __global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
 }
 
 template <typename TS, typename TC, int R, int W, int WY, int TX, int TY>
-hipError_t launch_box3_cfg(const PassArgs &p, hipStream_t stream)
+__global__ __launch_bounds__(TX *TY) void valu3d_box_kernel(
+    Box3Args<TC, Box3Cfg<TS, TC, R, W, WY, TX, TY>::K> a)
 {
     using Cfg = Box3Cfg<TS, TC, R, W, WY, TX, TY>;
-    static_assert(sizeof(Box3Args<TC, Cfg::K>) <= 4096, "weights exceed the kernel-argument block");
-    if (p.K != Cfg::K || p.steps != 1) return hipErrorInvalidValue;
-    Box3Args<TC, Cfg::K> a;
+    using Args = Box3Args<TC, Cfg::K>;
+    __shared__ __align__(16) TC lds[2][Cfg::PLANE + Cfg::VE];  // + VE: pad slot of the staging
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= a.ntiles) return;
+    const WPtr<TC> wk = (WPtr<TC>)((const __attribute__((address_space(4))) char *)
+                                       __builtin_amdgcn_kernarg_segment_ptr() +
+                                   offsetof(Args, w));
+    box3_tile<TS, TC, R, W, WY, TX, TY>(a, wk, tile, lds);
+}
+
+// Persistent batched launch over the tiles of several jobs (see the 3D
+// kernel of valu3d.hip); each job's weights are scalar-loaded from the job
+// table, which the kernel only reads.
+template <typename TS, typename TC, int R, int W, int WY, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void valu3d_box_batch_kernel(
+    const Box3Args<TC, Box3Cfg<TS, TC, R, W, WY, TX, TY>::K> *__restrict__ jobs,
+    const int *__restrict__ tile_start, int njobs)
+{
+    using Cfg = Box3Cfg<TS, TC, R, W, WY, TX, TY>;
+    using Args = Box3Args<TC, Cfg::K>;
+    __shared__ __align__(16) TC lds[2][Cfg::PLANE + Cfg::VE];
+    const int total = tile_start[njobs];
+    int j = 0;
+    for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
+        while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
+        const Args a = jobs[j];
+        const WPtr<TC> wk = (WPtr<TC>)((const __attribute__((address_space(4))) char *)(jobs + j) +
+                                       offsetof(Args, w));
+        box3_tile<TS, TC, R, W, WY, TX, TY>(a, wk, item - tile_start[j], lds);
+    }
+}
+
+template <typename TS, typename TC, int R, int W, int WY, int TX, int TY>
+bool box3_args(const PassArgs &p, Box3Args<TC, Box3Cfg<TS, TC, R, W, WY, TX, TY>::K> *out, hipError_t *err)
+{
+    using Cfg = Box3Cfg<TS, TC, R, W, WY, TX, TY>;
+    *err = hipSuccess;
+    if (p.K != Cfg::K || p.steps != 1) {
+        *err = hipErrorInvalidValue;
+        return false;
+    }
+    Box3Args<TC, Cfg::K> &a = *out;
     a.src = p.src;
     a.dst = p.dst;
     a.n0 = (int)p.dims[0];
@@ -279,8 +321,11 @@ hipError_t launch_box3_cfg(const PassArgs &p, hipStream_t stream)
     a.h = (TC)p.halo;
     for (int k = 0; k < Cfg::K; ++k) a.w[k] = (TC)p.w[k];
     const int D0 = a.oz1 - a.oz0, D1 = a.oy1 - a.oy0, D2 = a.ox1 - a.ox0;
-    if (D0 <= 0 || D1 <= 0 || D2 <= 0) return hipSuccess;
-    if ((int64_t)a.n1 * a.n2 > (1LL << 31) - 1) return hipErrorInvalidValue;  // in-plane offsets are int
+    if (D0 <= 0 || D1 <= 0 || D2 <= 0) return false;
+    if ((int64_t)a.n1 * a.n2 > (1LL << 31) - 1) {  // in-plane offsets are int
+        *err = hipErrorInvalidValue;
+        return false;
+    }
     a.nty = (D1 + Cfg::BY - 1) / Cfg::BY;
     a.ntx = (D2 + Cfg::BX - 1) / Cfg::BX;
     int BZ = p.tile_rows;
@@ -296,10 +341,60 @@ hipError_t launch_box3_cfg(const PassArgs &p, hipStream_t stream)
     a.BZ = BZ;
     a.nzs = (D0 + BZ - 1) / BZ;
     const int64_t nt = (int64_t)a.nzs * a.nty * a.ntx;
-    if (nt > (1LL << 30)) return hipErrorInvalidValue;
+    if (nt > (1LL << 30)) {
+        *err = hipErrorInvalidValue;
+        return false;
+    }
     a.ntiles = (int)nt;
+    return true;
+}
+
+template <typename TS, typename TC, int R, int W, int WY, int TX, int TY>
+hipError_t launch_box3_cfg(const PassArgs &p, hipStream_t stream)
+{
+    using Cfg = Box3Cfg<TS, TC, R, W, WY, TX, TY>;
+    static_assert(sizeof(Box3Args<TC, Cfg::K>) <= 4096, "weights exceed the kernel-argument block");
+    Box3Args<TC, Cfg::K> a;
+    hipError_t err;
+    if (!box3_args<TS, TC, R, W, WY, TX, TY>(p, &a, &err)) return err;
     hipLaunchKernelGGL((valu3d_box_kernel<TS, TC, R, W, WY, TX, TY>), dim3(a.ntiles), dim3(TX * TY), 0,
                        stream, a);
+    return hipGetLastError();
+}
+
+template <typename TS, typename TC, int R, int W, int WY, int TX, int TY>
+hipError_t launch_box3_batch_cfg(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
+{
+    using Cfg = Box3Cfg<TS, TC, R, W, WY, TX, TY>;
+    using Args = Box3Args<TC, Cfg::K>;
+    std::vector<Args> jobs;
+    std::vector<int> start(1, 0);
+    jobs.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        Args a;
+        hipError_t err;
+        if (!box3_args<TS, TC, R, W, WY, TX, TY>(ps[i], &a, &err)) {
+            if (err != hipSuccess) return err;
+            continue;
+        }
+        if ((int64_t)start.back() + a.ntiles > (1LL << 30)) return hipErrorInvalidValue;
+        jobs.push_back(a);
+        start.push_back(start.back() + a.ntiles);
+    }
+    if (jobs.empty()) return hipSuccess;
+    void *djobs = nullptr, *dstart = nullptr;
+    hipError_t e = stage_job_table(stage, jobs.data(), jobs.size() * sizeof(Args), start, &djobs, &dstart,
+                                   stream);
+    if (e != hipSuccess) return e;
+    int occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, valu3d_box_batch_kernel<TS, TC, R, W, WY, TX, TY>,
+                                                     TX * TY, 0);
+    if (e != hipSuccess || occ < 1) occ = 1;
+    const int slots = occ * (ps[0].num_cu > 0 ? ps[0].num_cu : 256);
+    const int total = start.back();
+    hipLaunchKernelGGL((valu3d_box_batch_kernel<TS, TC, R, W, WY, TX, TY>), dim3(total < slots ? total : slots),
+                       dim3(TX * TY), 0, stream, static_cast<const Args *>(djobs),
+                       static_cast<const int *>(dstart), (int)jobs.size());
     return hipGetLastError();
 }
 
@@ -316,7 +411,15 @@ hipError_t launch_box3(const PassArgs &p, hipStream_t stream)
     return launch_box3_cfg<TS, TC, R, W, 1, 16, (R >= 3 ? 16 : 32)>(p, stream);
 }
 
-#define B3(TS, TC, DT, R) {STENCIL_PATH_VALU, DT, STENCIL_BOX, 3, R, 1, &launch_box3<TS, TC, R>, nullptr}
+template <typename TS, typename TC, int R>
+hipError_t launch_box3_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
+{
+    constexpr int W = sizeof(TC) == 8 ? 2 : 4;
+    return launch_box3_batch_cfg<TS, TC, R, W, 1, 16, (R >= 3 ? 16 : 32)>(ps, n, stage, stream);
+}
+
+#define B3(TS, TC, DT, R) \
+    {STENCIL_PATH_VALU, DT, STENCIL_BOX, 3, R, 1, &launch_box3<TS, TC, R>, &launch_box3_batch<TS, TC, R>}
 
 }  // namespace
 

@@ -80,36 +80,23 @@ class _Active:
         self.bytes = nbytes
 
 
-def choose_T(stl, job, candidates=(1, 2, 3, 4)) -> int:
-    """Fusion depth with the best model prediction for the job's path (VALU
-    unless the job names one), among the depths the library fuses in one
-    pass, never more than the job's steps."""
-    path = job.path or "valu"
-    best, best_gst = 1, -1.0
-    for T in candidates:
-        if T > max(1, job.steps):
-            break
-        if T > 1 and not stl.kernel_available(path, job.dtype, job.shape, job.d, job.r, T):
-            continue
-        m = stl.model_predict(job.shape, job.d, job.r, T, job.dtype)
-        # a larger T also pays a skirt of r*T recomputed points per tile edge
-        gst = m["gst_valu"] * (1.0 - 0.02 * job.r * T)
-        if gst > best_gst:
-            best, best_gst = T, gst
-    return best
-
-
 class GpuExecutor:
     """Device work of the server, through the HIP library.
 
-    Jobs are spread over `streams` HIP streams (default priority): 2D jobs
-    share stream 0, where the passes of one kernel variant go out as one
-    batched launch; 3D jobs, which have no batched kernel, rotate over the
-    other streams so that their launches can overlap on the device when they
-    are too small to fill it.  A job stays on its stream, so its passes run in
-    order."""
+    Path, fusion depth T and VALU rows per workgroup come from the library's
+    model-seeded autotuner (stencil_plan_autotune: candidates ranked by the
+    roofline model, the best few timed on the job's own grid), run once per
+    problem class (shape, d, r, dtype, boundary and the grid side rounded to
+    a power of two) on the first job of the class and applied to the later
+    ones; a job that names T or a path keeps it.
 
-    def __init__(self, device="cuda", stream=None, streams=4):
+    Jobs are spread over `streams` HIP streams (default priority) by kernel
+    variant: all jobs of one variant share a stream, so their passes of a
+    round go out as one batched launch, while other variants' launches can
+    overlap with them on the device.  A job stays on its stream, so its passes
+    run in order."""
+
+    def __init__(self, device="cuda", stream=None, streams=4, autotune=True, tune_candidates=3):
         import torch
 
         import paper_2603_00477_amd as stl
@@ -120,15 +107,14 @@ class GpuExecutor:
         first = stream or torch.cuda.Stream(device=self.device)
         self.streams = [first] + [torch.cuda.Stream(device=self.device) for _ in range(max(0, streams - 1))]
         self.stream = first
-        self._rr = 0
-        self._plans = {}
+        self.autotune = bool(autotune)
+        self.tune_candidates = int(tune_candidates)
+        self.choices = {}  # problem class -> (path, T, rows, GStencil/s measured when tuned)
 
-    def _plan(self, job):
-        stl = self.stl
-        T = job.T or choose_T(stl, job)
-        p = stl.Plan(job.shape, job.d, job.r, job.weights, job.dims, T=T, dtype=job.dtype,
-                     boundary=job.boundary, path=job.path, halo=job.halo)
-        return p
+    @staticmethod
+    def problem_class(job):
+        side = max(int(x) for x in job.dims)
+        return (job.shape, job.d, job.r, job.dtype, job.boundary, int(round(np.log2(max(side, 1)))))
 
     def footprint(self, job) -> int:
         return 2 * self.output_bytes(job) + (1 << 20)
@@ -138,18 +124,26 @@ class GpuExecutor:
         D = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16x3": 4}[job.dtype]
         return int(np.prod(job.dims)) * D
 
-    def _stream_index(self, job) -> int:
-        if job.d == 2 or len(self.streams) == 1:
-            return 0
-        self._rr += 1
-        return 1 + self._rr % (len(self.streams) - 1)
+    def _stream_index(self, info) -> int:
+        """Stream of a kernel variant (all jobs of a variant on one stream)."""
+        key = (info["shape"], info["d"], info["r"], info["T"], info["dtype"], info["path"])
+        return hash(key) % len(self.streams)
 
     def prepare(self, job):
         torch = self.torch
-        plan = self._plan(job)
-        tdt = self.stl.torch_dtype(job.dtype)
-        si = self._stream_index(job)
-        with torch.cuda.stream(self.streams[si]):
+        stl = self.stl
+        plan = stl.Plan(job.shape, job.d, job.r, job.weights, job.dims, T=job.T or 1, dtype=job.dtype,
+                        boundary=job.boundary, path=job.path, halo=job.halo)
+        tdt = stl.torch_dtype(job.dtype)
+        key = self.problem_class(job)
+        tune = self.autotune and job.T is None and job.path is None
+        choice = self.choices.get(key) if tune else None
+        if choice is not None:
+            path, T, rows, _ = choice
+            plan.set(stl._abi.OPT_T, T)
+            plan.set(stl._abi.OPT_PATH, path)
+            plan.set(stl._abi.OPT_TILE_ROWS, rows)
+        with torch.cuda.stream(self.stream):
             if callable(job.data):
                 a = job.data(self.device)
             elif isinstance(job.data, torch.Tensor):
@@ -158,7 +152,18 @@ class GpuExecutor:
                 a = torch.as_tensor(np.asarray(job.data)).to(self.device)
             a = a.to(tdt).contiguous()
             b = torch.empty_like(a)
-        return {"plan": plan, "a": a, "b": b, "T": plan.info()["T"], "stream": si}
+        if tune and choice is None:
+            # first job of its class: time the model's best candidates on it
+            # (the probe runs overwrite b only)
+            g = plan.autotune(a, b, 8, max_candidates=self.tune_candidates, stream=self.stream)
+            i = plan.info()
+            self.choices[key] = (i["path"], i["T"], i.get("tile_rows", 0), g)
+        info = plan.info()
+        si = self._stream_index(info)
+        if si != 0:
+            # the grid was written on stream 0: the job's own stream waits for it
+            self.streams[si].wait_stream(self.stream)
+        return {"plan": plan, "a": a, "b": b, "T": info["T"], "stream": si}
 
     def run_round(self, states, steps):
         """One pass of every state (one batched call per stream used);

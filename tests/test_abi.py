@@ -166,3 +166,15 @@ def test_auto_path_follows_model():
     assert p.info()["path_name"] == "mfma"
     p2 = stl.Plan("box", 2, 3, si.normalised_weights(49, 2), (1024, 1024), T=1, dtype="f64")
     assert p2.info()["path_name"] == "valu"
+
+
+def test_plan_info_reports_tile_rows_and_fused_depth():
+    import paper_2603_00477_amd as stl
+    w = [1.0 / 49] * 49
+    p = stl.Plan("box", 2, 3, w, (64, 64), T=2, dtype="f64", path="valu", tile_rows=96)
+    i = p.info()
+    assert i["tile_rows"] == 96 and i["T_fused"] == 2
+    # float64 Star-2D3R fused 5 deep has no kernel: a pass runs as one-step launches
+    w13 = [1.0 / 13] * 13
+    q = stl.Plan("star", 2, 3, w13, (64, 64), T=5, dtype="f64", path="valu")
+    assert q.info()["T"] == 5 and q.info()["T_fused"] == 1
