@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--time-steps", type=int, default=100, help="stencil steps per sweep")
     ap.add_argument("--n", type=int, default=8192, help="grid side of the headline workload")
     ap.add_argument("--only", default="", help="comma list of headline variant names to run")
-    ap.add_argument("--sections", default="c2,c3,c4,c5,cases")
+    ap.add_argument("--sections", default="c2,c3,c4,c5,cases,sparse")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jobs", type=int, default=4096, help="served-stream jobs")
@@ -298,6 +298,51 @@ def section_cases(stl, args):
         log(f"case {case} {row['pattern']} T{T} {dt}: valu {row['valu'].get('gst', float('nan')):.1f} "
             f"(T={row['valu'].get('T_run')}), mfma {row.get('mfma', {}).get('gst', float('nan')):.1f}; "
             f"predicted {row['predicted']}, measured {row.get('measured', '-')}")
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------- dense vs 2:4 sparse matrix units
+# The paper's Table 4 compares one kernel on dense and on sparse Tensor Cores
+# (Box-2D1R fused 7 deep, float, Sec. "Further Acceleration with Sparse
+# Hardware"); gfx950's sparse instructions take 16-bit operands, so the MI355X
+# analogue runs bf16 storage with float32 accumulation, periodic grids, on the
+# dense band layout and on the 2:4 layout, next to the model's prediction
+# for each (sparse: the doubled matrix peak).
+SPARSE_CASES = [("box", 1, 7, 10240), ("box", 2, 3, 16384), ("box", 3, 2, 8192), ("star", 3, 2, 8192)]
+
+
+def section_sparse(stl, args):
+    import torch
+
+    import stencil_inputs as si
+
+    out = {}
+    for shape, r, T, n in SPARSE_CASES:
+        K = (2 * r + 1) ** 2 if shape == "box" else 4 * r + 1
+        w = si.normalised_weights(K, seed=si.weight_seed(6, 10 + r * 10 + T))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(si.data_seed(6, 10 + r * 10 + T))
+        x = torch.rand((n, n), generator=g, device="cuda", dtype=torch.float64).to(torch.bfloat16)
+        row = {}
+        for path in ("mfma", "mfma_sparse"):
+            v = dict(shape=shape, K=K, d=2, r=r, dtype="bf16", T=T, path=path, dims=(n, n), steps=4 * T,
+                     boundary="periodic")
+            res = measure(stl, v, x, w, 3, 1)
+            m = stl.model_predict(shape, 2, r, T, "bf16", sparse=(path == "mfma_sparse"))
+            if "gst" in res:
+                res["model_gst"] = m["gst_mfma"]
+                res["model_S"] = m["S"]
+            row[path] = res
+        name = f"{shape}-2d{r}r-bf16-T{T}-{n}"
+        if "gst" in row["mfma"] and "gst" in row["mfma_sparse"]:
+            row["speedup"] = row["mfma_sparse"]["gst"] / row["mfma"]["gst"]
+            row["model_speedup"] = row["mfma_sparse"]["model_gst"] / row["mfma"]["model_gst"]
+        out[name] = row
+        log(f"sparse {name}: dense {row['mfma'].get('gst', float('nan')):.1f}, sparse "
+            f"{row['mfma_sparse'].get('gst', float('nan')):.1f} GSt/s (measured x{row.get('speedup', float('nan')):.2f},"
+            f" model x{row.get('model_speedup', float('nan')):.2f})")
         del x
         torch.cuda.empty_cache()
     return out
@@ -613,7 +658,7 @@ def _sig(x, nd=3):
     return None if x is None else float(f"{float(x):.{nd}g}")
 
 
-def summaries(variants, mcheck, precision, serving, cases):
+def summaries(variants, mcheck, precision, serving, cases, sparse=None):
     """One-line summaries of every section for the JSON line (the full
     per-variant detail goes to --json-out / stderr)."""
     out = {}
@@ -635,6 +680,9 @@ def summaries(variants, mcheck, precision, serving, cases):
     if cases:
         out["paper_cases"] = {k: [_r(c.get("valu", {}).get("gst")), _r(c.get("mfma", {}).get("gst")),
                                   c["predicted"], c.get("measured")] for k, c in cases.items()}
+    if sparse:
+        out["sparse"] = {k: [_r(c.get("mfma", {}).get("gst")), _r(c.get("mfma_sparse", {}).get("gst")),
+                             _r(c.get("model_speedup"), 2)] for k, c in sparse.items()}
     return out
 
 
@@ -644,6 +692,7 @@ SUMMARY_KEYS = {
                  "(relative, against the FP64 oracle on a window after 1000 steps)",
     "serving": "served stream: [p50 ms, p99 ms, GStencil/s] at 0.8 load; capacity_gst [served, fifo]",
     "paper_cases": "Table 3 cases at 10240^2 / 1024^3: [VALU, MFMA GStencil/s, predicted, measured]",
+    "sparse": "Table 4 analogue, bf16 periodic: [dense MFMA, 2:4 sparse MFMA GStencil/s, model sparse/dense]",
 }
 
 
@@ -704,6 +753,7 @@ def main():
     c4 = section_c4(stl, args) if "c4" in sections else None
     c5 = section_serving(stl, args) if "c5" in sections else None
     cases = section_cases(stl, args) if "cases" in sections else None
+    sparse = section_sparse(stl, args) if "sparse" in sections else None
     cpu = None if args.no_cpu or not head_name else cpu_baseline(args.n, args.cpu_seconds)
     head = ok.get(head_name, {})
     roof = dict(head.get("roofline", {}))
@@ -713,6 +763,7 @@ def main():
     detail = {
         "headline": head_name, "roofline": roof or None, "cpu_baseline": cpu, "clocks": clocks,
         "variants": ok, "model_check": mcheck, "precision": c4, "serving": c5, "paper_cases": cases,
+        "sparse": sparse,
         "summary_keys": SUMMARY_KEYS,
     }
     s = json.dumps(detail)
@@ -722,7 +773,7 @@ def main():
     else:
         print("# detail " + s, file=sys.stderr, flush=True)
     print(compact_line(args, head_name, head, hv, roof, cpu, clocks,
-                       summaries(ok, mcheck, c4, c5, cases)), flush=True)
+                       summaries(ok, mcheck, c4, c5, cases, sparse)), flush=True)
 
 
 def headline_clocks(stl, args, hv):

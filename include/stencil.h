@@ -57,7 +57,17 @@ enum stencil_dtype {
 
 enum stencil_boundary { STENCIL_DIRICHLET = 0, STENCIL_PERIODIC = 1 };
 
-enum stencil_path { STENCIL_PATH_AUTO = 0, STENCIL_PATH_VALU = 1, STENCIL_PATH_MFMA = 2 };
+/* STENCIL_PATH_MFMA_SPARSE: the MFMA path on 2:4 structured-sparse matrix
+ * instructions (v_smfmac_f32_16x16x64, paper, Sec. "Further Acceleration with
+ * Sparse Hardware"): bf16/f16 storage, d = 2, composite radius r*T <= 7; one
+ * instruction covers two kernel columns of the band layout.  Never chosen by
+ * STENCIL_PATH_AUTO; the autotuner may pick it. */
+enum stencil_path {
+    STENCIL_PATH_AUTO = 0,
+    STENCIL_PATH_VALU = 1,
+    STENCIL_PATH_MFMA = 2,
+    STENCIL_PATH_MFMA_SPARSE = 3
+};
 
 enum stencil_status {
     STENCIL_OK = 0,
@@ -83,7 +93,7 @@ typedef struct stencil_plan_s *stencil_plan_t;
 /* Read-only description of a plan. */
 typedef struct {
     int shape, d, r, T, dtype, boundary;
-    int path;          /* resolved path: STENCIL_PATH_VALU or STENCIL_PATH_MFMA */
+    int path;          /* resolved path: STENCIL_PATH_VALU, _MFMA or _MFMA_SPARSE */
     int64_t dims[3];
     int K;             /* points of the single-step pattern                   */
     int K_T;           /* non-zero points of the T-step composite kernel      */
@@ -230,7 +240,9 @@ typedef struct {
     int dtype;       /* selects D (bytes per stored element) and gamma        */
     double S;        /* sparsity factor; <= 0 means: this library's layout    */
     double alpha;    /* redundancy factor; <= 0 means: K_T / (T K)            */
-    int sparse;      /* 1: use PP_mfma_sparse for the matrix side             */
+    int sparse;      /* 1: use PP_mfma_sparse for the matrix side, and (with S
+                        <= 0) the S of this library's 2:4 sparse layout
+                        where one exists (d = 2, 16-bit, r*T <= 7)           */
 } stencil_model_in_t;
 
 typedef struct {

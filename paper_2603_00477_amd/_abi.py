@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libstencil_mi355.so")
 STAR, BOX = 0, 1
 F64, F32, BF16, F16, F32_BF16X3 = 0, 1, 2, 3, 4
 DIRICHLET, PERIODIC = 0, 1
-PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
+PATH_AUTO, PATH_VALU, PATH_MFMA, PATH_MFMA_SPARSE = 0, 1, 2, 3
 OPT_PATH, OPT_HALO_VALUE, OPT_TILE_ROWS, OPT_T = 1, 2, 3, 4
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALIAS", 4: "OOM", 5: "HIP"}
 

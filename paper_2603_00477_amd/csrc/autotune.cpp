@@ -80,7 +80,7 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const void *in, void *
     // rank (path, T) by the model
     std::vector<Cand> cands;
     const int Tmax = (int)std::min<int64_t>(4, steps);
-    for (int path : {STENCIL_PATH_VALU, STENCIL_PATH_MFMA}) {
+    for (int path : {STENCIL_PATH_VALU, STENCIL_PATH_MFMA, STENCIL_PATH_MFMA_SPARSE}) {
         if (info.dtype == STENCIL_F32_BF16X3 && path == STENCIL_PATH_VALU) continue;
         for (int T = 1; T <= Tmax; ++T) {
             stencil_model_in_t mi;
@@ -90,6 +90,7 @@ extern "C" int stencil_plan_autotune(stencil_plan_t plan, const void *in, void *
             mi.r = info.r;
             mi.T = T;
             mi.dtype = info.dtype;
+            mi.sparse = path == STENCIL_PATH_MFMA_SPARSE;
             stencil_model_out_t mo;
             if (stencil_model_predict(&mi, nullptr, &mo)) continue;
             const double pred = path == STENCIL_PATH_VALU ? mo.gst_valu : mo.gst_mfma;

@@ -112,6 +112,22 @@ __device__ __forceinline__ v4f mfma16(v8h a, v8h b, v4f c)
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 v16bf __attribute__((ext_vector_type(16)));
+typedef _Float16 v16h __attribute__((ext_vector_type(16)));
+
+// 2:4 structured-sparse 16x16x64: `a` holds two of every four k positions of
+// lane l's row (positions in `idx`, 2 bits each), `b` 16 dense k values.
+__device__ __forceinline__ v4f smfma16(v8bf a, v16bf b, v4f c, int idx)
+{
+    return __builtin_amdgcn_smfmac_f32_16x16x64_bf16(a, b, c, idx, 0, 0);
+}
+__device__ __forceinline__ v4f smfma16(v8h a, v16h b, v4f c, int idx)
+{
+    return __builtin_amdgcn_smfmac_f32_16x16x64_f16(a, b, c, idx, 0, 0);
+}
+template <typename FR>
+using SparseB = typename std::conditional<std::is_same<FR, v8bf>::value, v16bf, v16h>::type;
+
 // storage value -> compute float/double
 template <typename TS>
 __device__ __forceinline__ auto load_val(TS v)
@@ -191,8 +207,10 @@ struct BandCols {
     static constexpr int PF = PF0 < 2 ? 2 : (PF0 > N ? N : PF0);
 };
 
-// One 16V x 16NW output tile of one pass, run by the whole workgroup.
-template <int DT, int SHAPE, int r, int T, int V, int NW>
+// One 16V x 16NW output tile of one pass, run by the whole workgroup.  SP:
+// 2:4 structured-sparse instructions, one per pair of kernel columns (16-bit
+// operands, composite radius <= 7; layout in mfma_layout.h).
+template <int DT, int SHAPE, int r, int T, int V, int NW, bool SP = false>
 __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
 {
     using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
@@ -213,7 +231,8 @@ __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
     // so the column loop reads A from LDS instead of from L2
     constexpr int NFRAG = band_total_frags(SHAPE, r, T, KDIM, 2);
     constexpr int NAF = NFRAG * (X3 ? 2 : 1);
-    constexpr bool ALDS = KDIM != 4 && NAF <= 24;
+    constexpr bool ALDS = KDIM != 4 && NAF <= 24 && !SP;
+    static_assert(!SP || (KDIM == 32 && !X3 && R <= sparse_max_radius()), "sparse layout: 16-bit, R <= 7");
     using FRS = typename MT::FR;
     __shared__ __attribute__((aligned(16))) FRS lA[ALDS ? NAF * 64 : 1];
 
@@ -251,6 +270,19 @@ __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
     if constexpr (KDIM == 4)
 #pragma unroll
         for (int j = 0; j < PF; ++j) load_col(j, j);
+    // sparse: compressed weights and positions of every column pair, in
+    // flight during the staging (at most 8 pairs: 40 VGPRs)
+    constexpr int NP = SP ? sparse_pairs(SHAPE, r, T) : 1;
+    FR Asp[NP];
+    int Isp[NP];
+    if constexpr (SP) {
+        const int *aidx = reinterpret_cast<const int *>(afr + NP * 64);
+#pragma unroll
+        for (int pi = 0; pi < NP; ++pi) {
+            Asp[pi] = afr[pi * 64 + lane];
+            Isp[pi] = aidx[pi * 64 + lane];
+        }
+    }
     // A table for the LDS copy: loads in flight during the staging
     constexpr int NAT = ALDS ? (NAF * 64 + NT - 1) / NT : 1;
     FR ta[NAT];
@@ -465,8 +497,31 @@ __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = ACC{};
 
+    if constexpr (SP) {
+        // pair (b0, b1): lane (lg, ln) supplies rows 4lg..4lg+3 and
+        // 4lg+16..4lg+19 of both columns' 32-row blocks, interleaved two rows
+        // at a time: k positions 8lg..8lg+7 (column b0) and 32+8lg..32+8lg+7
+        // (column b1) of the instruction's dense k
 #pragma unroll
-    for (int j = 0; j < Cols::N; ++j) {
+        for (int pi = 0; pi < NP; ++pi) {
+            const int b0 = Cols::col(2 * pi);
+            const int b1 = 2 * pi + 1 < Cols::N ? Cols::col(2 * pi + 1) : b0;
+            const int col0 = wc0 + ln + b0 + R, col1 = wc0 + ln + b1 + R;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int row = 16 * v + 4 * lg;
+                const uint2 x0 = *reinterpret_cast<const uint2 *>(&lhi[col0 * LR + row]);
+                const uint2 x1 = *reinterpret_cast<const uint2 *>(&lhi[col0 * LR + row + 16]);
+                const uint2 y0 = *reinterpret_cast<const uint2 *>(&lhi[col1 * LR + row]);
+                const uint2 y1 = *reinterpret_cast<const uint2 *>(&lhi[col1 * LR + row + 16]);
+                typedef unsigned v8u __attribute__((ext_vector_type(8)));
+                const v8u Bw = {x0.x, x1.x, x0.y, x1.y, y0.x, y1.x, y0.y, y1.y};
+                acc[v] = smfma16(Asp[pi], __builtin_bit_cast(SparseB<FR>, Bw), acc[v], Isp[pi]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < (SP ? 0 : Cols::N); ++j) {
         const int b = Cols::col(j);
         const int klo = band_kk_lo(SHAPE, r, T, 0, b, KDIM);
         const int khi = band_kk_hi(SHAPE, r, T, 0, b, KDIM);
@@ -520,19 +575,19 @@ __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
     }
 }
 
-template <int DT, int SHAPE, int r, int T, int V, int NW>
+template <int DT, int SHAPE, int r, int T, int V, int NW, bool SP>
 __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= a.ntiles) return;
-    mfma2d_tile<DT, SHAPE, r, T, V, NW>(a, tile);
+    mfma2d_tile<DT, SHAPE, r, T, V, NW, SP>(a, tile);
 }
 
 // Persistent batched launch over the tiles of several jobs: workgroup b takes
 // items b + i*gridDim of one list; tile_start[j] is the first item of job j
 // (tile_start[njobs] = total).  A barrier between items keeps the next
 // item's staging from overwriting LDS blocks still being read.
-template <int DT, int SHAPE, int r, int T, int V, int NW>
+template <int DT, int SHAPE, int r, int T, int V, int NW, bool SP>
 __global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs *__restrict__ jobs,
                                                              const int *__restrict__ tile_start, int njobs)
 {
@@ -541,7 +596,7 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs 
     for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
         const Mfma2DArgs a = jobs[j];
-        mfma2d_tile<DT, SHAPE, r, T, V, NW>(a, item - tile_start[j]);
+        mfma2d_tile<DT, SHAPE, r, T, V, NW, SP>(a, item - tile_start[j]);
         __syncthreads();
     }
 }
@@ -578,20 +633,20 @@ bool mfma2d_args(const PassArgs &p, Mfma2DArgs *out)
     return true;
 }
 
-template <int DT, int SHAPE, int r, int T>
+template <int DT, int SHAPE, int r, int T, bool SP = false>
 hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
 {
     constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
     Mfma2DArgs a;
     if (!mfma2d_args<DT, SHAPE, r, T>(p, &a)) return hipErrorInvalidValue;
     if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW>), dim3(a.ntiles), dim3(64 * NW), 0,
+    hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW, SP>), dim3(a.ntiles), dim3(64 * NW), 0,
                        stream, a);
     return hipGetLastError();
 }
 
 // n passes (one per job) of this variant in one persistent launch.
-template <int DT, int SHAPE, int r, int T>
+template <int DT, int SHAPE, int r, int T, bool SP = false>
 hipError_t launch_mfma2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
     constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
@@ -612,12 +667,12 @@ hipError_t launch_mfma2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
                                    &dstart, stream);
     if (e != hipSuccess) return e;
     int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, mfma2d_batch_kernel<DT, SHAPE, r, T, V, NW>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, mfma2d_batch_kernel<DT, SHAPE, r, T, V, NW, SP>,
                                                      64 * NW, 0);
     if (e != hipSuccess || occ < 1) occ = 1;
     const int slots = occ * (ps[0].num_cu > 0 ? ps[0].num_cu : 256);
     const int total = start.back();
-    hipLaunchKernelGGL((mfma2d_batch_kernel<DT, SHAPE, r, T, V, NW>), dim3(total < slots ? total : slots),
+    hipLaunchKernelGGL((mfma2d_batch_kernel<DT, SHAPE, r, T, V, NW, SP>), dim3(total < slots ? total : slots),
                        dim3(64 * NW), 0, stream, static_cast<const Mfma2DArgs *>(djobs),
                        static_cast<const int *>(dstart), (int)jobs.size());
     return hipGetLastError();
@@ -628,5 +683,14 @@ hipError_t launch_mfma2d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
 #define M2_T(DT, SH, R) M2(DT, SH, R, 1), M2(DT, SH, R, 2), M2(DT, SH, R, 3), M2(DT, SH, R, 4)
 #define M2_R(DT, SH) M2_T(DT, SH, 1), M2_T(DT, SH, 2), M2_T(DT, SH, 3)
 #define M2_S(DT) M2_R(DT, STENCIL_STAR), M2_R(DT, STENCIL_BOX)
+
+// 2:4 structured-sparse instances (composite radius <= 7)
+#define M2SP(DT, SH, R, T)                                                                  \
+    {STENCIL_PATH_MFMA_SPARSE, DT, SH, 2, R, T, &launch_mfma2d<DT, SH, R, T, true>,         \
+     &launch_mfma2d_batch<DT, SH, R, T, true>}
+#define M2SP_S(DT, SH)                                                                      \
+    M2SP(DT, SH, 1, 1), M2SP(DT, SH, 1, 2), M2SP(DT, SH, 1, 3), M2SP(DT, SH, 1, 4),           \
+        M2SP(DT, SH, 1, 7), M2SP(DT, SH, 2, 1), M2SP(DT, SH, 2, 2), M2SP(DT, SH, 2, 3),       \
+        M2SP(DT, SH, 3, 1), M2SP(DT, SH, 3, 2)
 
 }  // namespace stl

@@ -8,6 +8,7 @@
 // operand type (round to nearest even).  The compensated mode stores
 // hi = bf16(w) and lo = bf16(w - hi).
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -112,6 +113,63 @@ void mfma_build_fragments(int shape, int d, int r, const double *w, int steps, i
                     }
                 }
             }
+        }
+    }
+}
+
+void mfma_build_sparse_fragments(int shape, int r, const double *w, int steps, int dtype,
+                                 std::vector<uint8_t> *out)
+{
+    // Per column pair: 64 lanes x 8 compressed 16-bit weights, then 64 lanes
+    // x one int32 of 2-bit positions.  Lane l holds output row m = l % 16 and
+    // groups g = 4 (l / 16) + j / 2 (j = 0..7; groups 0-7 column b, 8-15
+    // column b'); value j's position within its group is bits 2j..2j+1.
+    out->clear();
+    const int R = r * steps;
+    const int side = 2 * R + 1;
+    std::vector<double> wc;
+    compose_dense(shape, 2, r, w, steps, &wc);
+    std::vector<int> cols;
+    for (int b = -R; b <= R; ++b)
+        if (band_amax(shape, r, steps, 0, b) >= 0) cols.push_back(b);
+    const int np = (int)(cols.size() + 1) / 2;
+    out->assign((size_t)np * 64 * (16 + 4), 0);
+    uint8_t *vals = out->data();
+    uint8_t *idxs = out->data() + (size_t)np * 64 * 16;
+    for (int pi = 0; pi < np; ++pi) {
+        const int cb[2] = {cols[2 * pi], 2 * pi + 1 < (int)cols.size() ? cols[2 * pi + 1] : cols[2 * pi]};
+        const bool second_empty = 2 * pi + 1 >= (int)cols.size();
+        for (int l = 0; l < 64; ++l) {
+            const int m = l % 16, q = l / 16;
+            uint32_t idx = 0;
+            for (int gg = 0; gg < 4; ++gg) {
+                const int g = 4 * q + gg;
+                const int half = g / 8, h = g % 8;
+                const int b = cb[half];
+                double v[4];
+                for (int e = 0; e < 4; ++e) {
+                    const int a = sparse_group_row(h, e) - m - R;  // row offset of the weight
+                    v[e] = 0.0;
+                    if (!(half == 1 && second_empty) && a >= -R && a <= R)
+                        v[e] = wc[(size_t)(a + R) * side + (b + R)];
+                }
+                // the (at most two) non-zero positions, padded with zero
+                // weights at free positions, in ascending order
+                int pos[2], n = 0;
+                for (int e = 0; e < 4 && n < 2; ++e)
+                    if (v[e] != 0.0) pos[n++] = e;
+                for (int e = 0; e < 4 && n < 2; ++e)
+                    if (v[e] == 0.0 && (n == 0 || pos[0] != e)) pos[n++] = e;
+                if (pos[0] > pos[1]) std::swap(pos[0], pos[1]);
+                for (int s = 0; s < 2; ++s) {
+                    const int j = 2 * gg + s;
+                    const double x = v[pos[s]];
+                    const uint16_t bits = dtype == STENCIL_F16 ? f16_bits(x) : bf16_bits(x);
+                    std::memcpy(vals + ((size_t)(pi * 64 + l) * 8 + j) * 2, &bits, 2);
+                    idx |= (uint32_t)pos[s] << (2 * j);
+                }
+            }
+            std::memcpy(idxs + (size_t)(pi * 64 + l) * 4, &idx, 4);
         }
     }
 }

@@ -72,6 +72,29 @@ __host__ __device__ constexpr int band_total_frags(int shape, int r, int t, int 
     return off;
 }
 
+// 2:4 structured-sparse layout (d = 2, 16-bit operands, composite radius
+// R <= 7).  One v_smfmac_f32_16x16x64 covers two non-empty kernel columns
+// (b, b') of a 16-row output tile: its 64 dense k positions are 16 groups of
+// four; group h < 8 holds rows {2h, 2h+1, 2h+16, 2h+17} of column b's
+// 32-row data block, group 8 + h the same rows of column b'.  A band of at
+// most 15 rows never covers two rows of a group 15 or more apart, so every
+// group holds at most two non-zero weights, as the instruction requires.
+// Columns pair in order; an odd last column pairs with itself, its second
+// half weighted zero.
+__host__ __device__ constexpr int sparse_max_radius() { return 7; }
+
+__host__ __device__ constexpr int band_ncols(int shape, int r, int t)
+{
+    int n = 0;
+    for (int b = -r * t; b <= r * t; ++b) n += band_amax(shape, r, t, 0, b) >= 0 ? 1 : 0;
+    return n;
+}
+
+__host__ __device__ constexpr int sparse_pairs(int shape, int r, int t) { return (band_ncols(shape, r, t) + 1) / 2; }
+
+// Row of the 32-row data block held at position e (0..3) of group h (0..7).
+__host__ __device__ constexpr int sparse_group_row(int h, int e) { return 2 * h + (e & 1) + 16 * (e >> 1); }
+
 // k of the MFMA instruction for a storage dtype (STENCIL_* codes).
 __host__ __device__ constexpr int mfma_kdim(int dtype) { return dtype <= 1 ? 4 : 32; }
 

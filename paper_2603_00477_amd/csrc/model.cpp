@@ -150,7 +150,16 @@ extern "C" int stencil_model_predict(const stencil_model_in_t *in, const stencil
     o.K_T = (int)fused_points(in->shape, in->d, in->r, T);
     o.D = dtype_bytes(in->dtype);
     o.alpha = in->alpha > 0 ? in->alpha : (double)o.K_T / ((double)T * o.K);
-    o.S = in->S > 0 ? in->S : mfma_layout(in->shape, in->d, in->r, T, in->dtype).S;
+    if (in->S > 0) {
+        o.S = in->S;
+    } else if (in->sparse && in->d == 2 && mfma_k(in->dtype) == 32 && in->dtype != STENCIL_F32_BF16X3 &&
+               in->r * T <= sparse_max_radius()) {
+        // 2:4 layout: one 16x16x64 instruction (64 dense-equivalent MACs per
+        // output point, counted against the sparse peak) per column pair
+        o.S = (double)o.K_T / (64.0 * sparse_pairs(in->shape, in->r, T));
+    } else {
+        o.S = mfma_layout(in->shape, in->d, in->r, T, in->dtype).S;
+    }
     o.gamma = in->dtype == STENCIL_F32_BF16X3 ? 3.0 : 1.0;
     const double PPm = in->sparse ? H.PP_mfma_sparse : H.PP_mfma;
     o.C_valu = 2.0 * o.K * T;

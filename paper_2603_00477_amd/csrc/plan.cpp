@@ -154,11 +154,12 @@ bool has_path(int path, int dtype, int shape, int d, int r, int T)
     if (path == STENCIL_PATH_VALU)
         return find_kernel(STENCIL_PATH_VALU, dtype, shape, d, r, T) != nullptr ||
                find_kernel(STENCIL_PATH_VALU, dtype, shape, d, r, 1) != nullptr;
-    return find_kernel(STENCIL_PATH_MFMA, dtype, shape, d, r, T) != nullptr;
+    return find_kernel(path, dtype, shape, d, r, T) != nullptr;
 }
 
-// Model results for the plan's (shape, d, r, T, dtype).
-void plan_model(stencil_plan_s *p)
+// Model results for the plan's (shape, d, r, T, dtype); `sparse`: the matrix
+// side on 2:4 structured-sparse instructions (its peak and layout).
+void plan_model(stencil_plan_s *p, bool sparse = false)
 {
     stencil_model_in_t mi;
     std::memset(&mi, 0, sizeof mi);
@@ -167,6 +168,7 @@ void plan_model(stencil_plan_s *p)
     mi.r = p->r;
     mi.T = p->T;
     mi.dtype = p->dtype;
+    mi.sparse = sparse ? 1 : 0;
     stencil_model_out_t mo;
     stencil_model_predict(&mi, nullptr, &mo);
     p->K_T = mo.K_T;
@@ -183,6 +185,7 @@ int resolve_path(stencil_plan_s *p)
 {
     const bool v = has_path(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T);
     const bool m_built = has_path(STENCIL_PATH_MFMA, p->dtype, p->shape, p->d, p->r, p->T);
+    const bool sp_built = has_path(STENCIL_PATH_MFMA_SPARSE, p->dtype, p->shape, p->d, p->r, p->T);
     // a kernel-fused Dirichlet pass needs a VALU kernel of the same depth for
     // its boundary band (launch_fixup)
     const bool band_ok = p->boundary == STENCIL_PERIODIC || p->T == 1 ||
@@ -199,13 +202,16 @@ int resolve_path(stencil_plan_s *p)
         return fail(STENCIL_ERR_UNSUPPORTED, "VALU path not built for this dtype/shape/d/r");
     if (path == STENCIL_PATH_MFMA && !m_built)
         return fail(STENCIL_ERR_UNSUPPORTED, "MFMA path not built for this dtype/shape/d/r/T");
-    if (path == STENCIL_PATH_MFMA && !band_ok)
+    if (path == STENCIL_PATH_MFMA_SPARSE && !sp_built)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "2:4 sparse MFMA path not built for this dtype/shape/d/r/T (bf16/f16, d = 2, r*T <= 7)");
+    if (is_mfma_path(path) && !band_ok)
         return fail(STENCIL_ERR_UNSUPPORTED,
                     "Dirichlet MFMA plan needs a fused VALU kernel of the same T for its boundary band; "
                     "use a periodic boundary or another T");
     if (p->dtype == STENCIL_F32_BF16X3 && path != STENCIL_PATH_MFMA)
         return fail(STENCIL_ERR_UNSUPPORTED, "bf16x3 is an MFMA-only mode");
-    if (path == STENCIL_PATH_MFMA && p->boundary == STENCIL_PERIODIC)
+    if (is_mfma_path(path) && p->boundary == STENCIL_PERIODIC)
         for (int i = 0; i < p->d; ++i)
             if (p->dims[i] < 2 * (int64_t)p->r * p->T + 1)
                 return fail(STENCIL_ERR_INVALID_ARG,
@@ -229,13 +235,26 @@ void free_device(stencil_plan_s *p)
 
 size_t grid_bytes(const stencil_plan_s *p) { return (size_t)p->npts * dtype_bytes(p->dtype); }
 
+// Operand fragments of the plan's path for a pass of t steps (empty for a
+// depth the path has no kernel for).
+void build_fragments(const stencil_plan_s *p, int t, std::vector<uint8_t> *hi, std::vector<uint8_t> *lo)
+{
+    hi->clear();
+    lo->clear();
+    if (!find_kernel(p->path, p->dtype, p->shape, p->d, p->r, t)) return;
+    if (p->path == STENCIL_PATH_MFMA_SPARSE)
+        mfma_build_sparse_fragments(p->shape, p->r, p->w.data(), t, p->dtype, hi);
+    else
+        mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), t, p->dtype, hi, lo);
+}
+
 size_t fragment_bytes(const stencil_plan_s *p)
 {
-    if (p->path != STENCIL_PATH_MFMA) return 0;
+    if (!is_mfma_path(p->path)) return 0;
     size_t total = 0;
     for (int t = 1; t <= p->T; ++t) {
         std::vector<uint8_t> hi, lo;
-        mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), t, p->dtype, &hi, &lo);
+        build_fragments(p, t, &hi, &lo);
         total += hi.size() + lo.size();
     }
     return total;
@@ -270,13 +289,12 @@ int ensure_device(stencil_plan_s *p, bool need_scratch)
 int upload_fragments(stencil_plan_s *p)
 {
     hipError_t e;
-    if (p->path == STENCIL_PATH_MFMA) {
+    if (is_mfma_path(p->path)) {
         p->afrag.assign(p->T + 1, nullptr);
         p->afrag_lo.assign(p->T + 1, nullptr);
         for (int t = 1; t <= p->T; ++t) {
-            if (!find_kernel(STENCIL_PATH_MFMA, p->dtype, p->shape, p->d, p->r, t)) continue;
             std::vector<uint8_t> hi, lo;
-            mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), t, p->dtype, &hi, &lo);
+            build_fragments(p, t, &hi, &lo);
             for (int part = 0; part < 2; ++part) {
                 const std::vector<uint8_t> &v = part ? lo : hi;
                 if (v.empty()) continue;
@@ -318,12 +336,12 @@ std::vector<PassDesc> schedule(const stencil_plan_s *p, int64_t steps)
     for (int t : depths) {
         const KernelEntry *k = find_kernel(p->path, p->dtype, p->shape, p->d, p->r, t);
         int path = p->path;
-        if (!k && path == STENCIL_PATH_MFMA) {
+        if (!k && is_mfma_path(path)) {
             k = find_kernel(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, t);
             path = STENCIL_PATH_VALU;
         }
         if (k) {
-            const bool fix = path == STENCIL_PATH_MFMA && p->boundary == STENCIL_DIRICHLET && t > 1;
+            const bool fix = is_mfma_path(path) && p->boundary == STENCIL_DIRICHLET && t > 1;
             out.push_back({path, t, k, fix});
         } else {
             const KernelEntry *k1 = find_kernel(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, 1);
@@ -413,7 +431,7 @@ int run_one(stencil_plan_s *p, const void *in, void *out, int64_t steps, hipStre
         PassArgs a = base_args(p, pd.t);
         a.src = src;
         a.dst = dst;
-        if (pd.path == STENCIL_PATH_MFMA) {
+        if (is_mfma_path(pd.path)) {
             a.afrag = p->afrag[pd.t];
             a.afrag_lo = p->afrag_lo[pd.t];
         }
@@ -485,7 +503,7 @@ int run_batch(int n, const stencil_plan_t *plans, const void *const *ins, void *
             a.src = src[i];
             a.dst = dst;
             src[i] = dst;
-            if (pd.path == STENCIL_PATH_MFMA) {
+            if (is_mfma_path(pd.path)) {
                 a.afrag = p->afrag[pd.t];
                 a.afrag_lo = p->afrag_lo[pd.t];
             }
@@ -540,7 +558,7 @@ int run_without_allocation(stencil_plan_s *p, const void *in, void *out, int64_t
     if (e != hipSuccess) return fail(STENCIL_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     if (p->device != dev) {
         // only the MFMA operand fragments would need device memory
-        if (p->path == STENCIL_PATH_MFMA)
+        if (is_mfma_path(p->path))
             return fail(STENCIL_ERR_UNSUPPORTED,
                         "stencil_run_noalloc: this MFMA plan has no operand fragments on the current "
                         "device; run it once with stencil_run there first (that call uploads them)");
@@ -555,7 +573,7 @@ extern "C" const char *stencil_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int stencil_kernel_available(int path, int dtype, int shape, int d, int r, int T)
 {
-    if ((path != STENCIL_PATH_VALU && path != STENCIL_PATH_MFMA) || !valid_dtype(dtype) ||
+    if ((path != STENCIL_PATH_VALU && !is_mfma_path(path)) || !valid_dtype(dtype) ||
         (shape != STENCIL_STAR && shape != STENCIL_BOX) || (d != 2 && d != 3) || r < 1 || T < 1)
         return 0;
     return find_kernel(path, dtype, shape, d, r, T) != nullptr ? 1 : 0;
@@ -659,7 +677,7 @@ extern "C" int stencil_plan_set(stencil_plan_t p, int option, double value)
         if ((double)v != value) return fail(STENCIL_ERR_INVALID_ARG, "integer option expected");
         const int old_req = p->path_req, old_path = p->path, old_T = p->T;
         if (option == STENCIL_OPT_PATH) {
-            if (v < STENCIL_PATH_AUTO || v > STENCIL_PATH_MFMA)
+            if (v < STENCIL_PATH_AUTO || v > STENCIL_PATH_MFMA_SPARSE)
                 return fail(STENCIL_ERR_INVALID_ARG, "unknown path");
             p->path_req = v;
         } else {
@@ -672,9 +690,11 @@ extern "C" int stencil_plan_set(stencil_plan_t p, int option, double value)
             p->path_req = old_req;
             p->path = old_path;
             p->T = old_T;
-            plan_model(p);
+            plan_model(p, p->path == STENCIL_PATH_MFMA_SPARSE);
             return rc;
         }
+        // model results of the resolved path (the sparse path's peak and layout)
+        plan_model(p, p->path == STENCIL_PATH_MFMA_SPARSE);
         free_device(p);
         p->afrag_bytes = fragment_bytes(p);
         return STENCIL_OK;
@@ -710,7 +730,7 @@ extern "C" int stencil_plan_info(stencil_plan_t p, stencil_plan_info_t *out)
     i.scenario = p->scenario;
     i.tile_rows = p->tile_rows;
     const bool fused = find_kernel(p->path, p->dtype, p->shape, p->d, p->r, p->T) != nullptr ||
-                       (p->path == STENCIL_PATH_MFMA &&
+                       (is_mfma_path(p->path) &&
                         find_kernel(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T) != nullptr);
     i.T_fused = fused ? p->T : 1;
     *out = i;

@@ -178,3 +178,27 @@ def test_plan_info_reports_tile_rows_and_fused_depth():
     w13 = [1.0 / 13] * 13
     q = stl.Plan("star", 2, 3, w13, (64, 64), T=5, dtype="f64", path="valu")
     assert q.info()["T"] == 5 and q.info()["T_fused"] == 1
+
+
+def test_sparse_path_model_and_availability():
+    # Box-2D1R fused 7 deep in bf16: 15 kernel columns -> 8 column pairs of one
+    # 16x16x64 instruction each; S = K_T / (64 * 8) against the sparse peak
+    m = stl.model_predict("box", 2, 1, 7, "bf16", sparse=True)
+    assert m["K_T"] == 225 and m["S"] == pytest.approx(225 / 512)
+    dense = stl.model_predict("box", 2, 1, 7, "bf16")
+    assert dense["S"] == pytest.approx(225 / (15 * 32))
+    # same issued dense-equivalent work, twice the peak: the matrix ceiling doubles
+    assert m["P_mfma_raw"] >= dense["P_mfma_raw"]
+    assert stl.kernel_available("mfma_sparse", "bf16", "box", 2, 1, 7)
+    assert stl.kernel_available("mfma_sparse", "f16", "star", 2, 2, 2)
+    assert not stl.kernel_available("mfma_sparse", "bf16", "box", 2, 2, 4)   # composite radius 8
+    assert not stl.kernel_available("mfma_sparse", "f32", "box", 2, 1, 1)
+    p = stl.Plan("box", 2, 1, [1 / 9] * 9, (64, 64), T=7, dtype="bf16", path="mfma_sparse", boundary="periodic")
+    i = p.info()
+    assert i["path_name"] == "mfma_sparse" and i["S"] == pytest.approx(225 / 512)
+    # Box-2D2R fused 3 deep: 13 columns, 7 pairs; switching to the dense path
+    # gives the dense layout's S again
+    q = stl.Plan("box", 2, 2, [1 / 25] * 25, (64, 64), T=3, dtype="bf16", path="mfma_sparse", boundary="periodic")
+    assert q.info()["S"] == pytest.approx(169 / 448)
+    q.set(stl._abi.OPT_PATH, stl.PATH_MFMA)
+    assert q.info()["path_name"] == "mfma" and q.info()["S"] == pytest.approx(169 / 416)

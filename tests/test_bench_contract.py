@@ -138,7 +138,10 @@ def test_json_line_is_small_and_complete():
            "sample": "Box-2D3R f64 8192x8192, 16 time steps (of 100), zero Dirichlet halo",
            "cpu_model": "AMD EPYC 9575F 64-Core Processor", "nproc": 256, "affinity": 16}
     clocks = {"sclk_mhz": 2400, "mclk_mhz": 1900, "fclk_mhz": 2000, "socclk_mhz": 1200}
-    summ = bench.summaries(variants, mcheck, precision, serving, cases)
+    sparse = {f"box-2d{r}r-bf16-T{T}-{n}": {"mfma": {"gst": 1234.567}, "mfma_sparse": {"gst": 1534.567},
+                                            "model_speedup": 1.25} for r, T, n in ((1, 7, 10240), (2, 3, 16384),
+                                                                                   (3, 2, 8192), (3, 2, 8193))}
+    summ = bench.summaries(variants, mcheck, precision, serving, cases, sparse)
     s = bench.compact_line(args, head_name, variants[head_name], hv, roof, cpu, clocks, summ)
     assert len(s.encode()) <= 4096, len(s)
     line = json.loads(s)

@@ -157,6 +157,8 @@ def test_workload_16384_precision_1000_steps(stl, dt):
     u0 = si.smooth_grid((n, n), seed=si.data_seed(4, 0))
     w = si.normalised_weights(25, seed=si.weight_seed(4, 0))
     assert np.array_equal(np.asarray(g["weights"]), w)
+    import hashlib
+    assert hashlib.sha1(u0.tobytes()).hexdigest() == g["u0_sha1"]
     store = {"bf16": "bf16", "f16": "f16", "bf16x3": "f32"}[dt]
     u0r, t = si.round_to(u0, store)
     wins = windows2d(n)[:5]
@@ -190,4 +192,37 @@ def test_workload_16384_precision_1000_steps(stl, dt):
         print(f"[fullsize] {dt} after {st} steps: arithmetic error {arith:.3e} (bound {bound:.3e}), "
               f"end-to-end error {e2e:.3e}", flush=True)
         assert arith <= bound, (dt, st, arith, bound)
+    p.close()
+
+
+def test_workload_16384_f64_reference_1000_steps(stl):
+    """The float64 VALU sweep the benchmark uses as the whole-grid reference
+    of the precision workload (T = 2, 1000 steps in ten runs of 100) equals
+    the FP64 oracle on the stored window after 1000 steps and on live windows
+    after 100 steps (relative 1e-12)."""
+    import torch
+    n = 16384
+    g = _golden16384()
+    u0 = si.smooth_grid((n, n), seed=si.data_seed(4, 0))
+    w = si.normalised_weights(25, seed=si.weight_seed(4, 0))
+    wins = windows2d(n)[:5]
+    ref100 = [ocore.run_window("box", 2, 2, w, u0, 100, lo, hi, "periodic") for lo, hi in wins]
+    p = stl.Plan("box", 2, 2, w, (n, n), T=2, dtype="f64", path="valu", boundary="periodic")
+    x = torch.from_numpy(u0).to("cuda")
+    y = torch.empty_like(x)
+    print(f"[fullsize] box-2d2r f64 T=2 valu {n}^2 periodic, 10 x 100 steps", flush=True)
+    for k in range(10):
+        p.run(x, y, 100)
+        x, y = y, x
+        if k == 0:
+            got = [x[_slice(a, b)].cpu().numpy() for a, b in wins]
+            scale = max(float(np.max(np.abs(rf))) for rf in ref100)
+            err = max(float(np.max(np.abs(gg - rf))) for gg, rf in zip(got, ref100)) / scale
+            assert err <= 1e-12, err
+    torch.cuda.synchronize()
+    lo, hi = g["lo"], g["hi"]
+    gw = np.asarray(g["windows"]["f64"]["values"])
+    err = float(np.max(np.abs(x[_slice(lo, hi)].cpu().numpy() - gw)) / np.max(np.abs(gw)))
+    print(f"[fullsize] f64 reference after 1000 steps: {err:.2e}", flush=True)
+    assert err <= 1e-12, err
     p.close()

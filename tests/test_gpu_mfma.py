@@ -165,3 +165,46 @@ def test_mfma3d_small_periodic(stl, shape, r, T, dims):
     got = run_gpu(p, t, 2 * T)
     ref = oracle(shape, 3, r, w, u0, 2 * T, "periodic")
     assert rel_inf(got, ref) <= 1e-12
+
+
+SPARSE_CASES = [("box", 1, 1), ("box", 1, 4), ("box", 1, 7), ("box", 2, 3), ("box", 3, 2), ("star", 1, 3),
+                ("star", 2, 2), ("star", 3, 1)]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("shape,r,T", SPARSE_CASES)
+@pytest.mark.parametrize("boundary", ["periodic", "dirichlet"])
+def test_mfma2d_sparse(stl, dt, shape, r, T, boundary):
+    """2:4 structured-sparse MFMA (one v_smfmac per pair of kernel columns):
+    arithmetic error against the oracle on the rounded data within the same
+    bound as the dense 16-bit kernels, over two full passes and a remainder
+    pass; Dirichlet plans of depths without a fused 16-bit VALU kernel for
+    the boundary band are refused."""
+    dims = (150, 217)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6600 + 10 * r + T)
+    steps = 2 * T + 1
+    if boundary == "dirichlet" and T > 4:
+        with pytest.raises(stl.StencilError) as e:
+            stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma_sparse", boundary=boundary)
+        assert e.value.status == "UNSUPPORTED"
+        return
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma_sparse", boundary=boundary)
+    assert p.info()["path_name"] == "mfma_sparse"
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0r, steps, boundary)
+    err = float(np.max(np.abs(got - ref)))
+    assert err <= _bound(dt, shape, 2, r, T, steps, float(np.max(np.abs(u0r)))), err
+    # the dense kernel computes the same products (summed in another order)
+    q = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma", boundary=boundary)
+    dense = run_gpu(q, t, steps)
+    assert float(np.max(np.abs(dense - ref))) <= _bound(dt, shape, 2, r, T, steps, float(np.max(np.abs(u0r))))
+
+
+def test_mfma2d_sparse_refusals(stl):
+    w = si_weights = np.full(25, 1 / 25)
+    # composite radius 8 does not fit the 2:4 layout; float32 has no sparse instruction
+    for dt, r, T in (("bf16", 2, 4), ("f32", 1, 2)):
+        with pytest.raises(stl.StencilError) as e:
+            stl.Plan("box", 2, r, np.full((2 * r + 1) ** 2, 1.0 / (2 * r + 1) ** 2), (64, 64), T=T, dtype=dt,
+                     path="mfma_sparse", boundary="periodic")
+        assert e.value.status == "UNSUPPORTED"
