@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--time-steps", type=int, default=100, help="stencil steps per sweep")
     ap.add_argument("--n", type=int, default=8192, help="grid side of the headline workload")
     ap.add_argument("--only", default="", help="comma list of headline variant names to run")
-    ap.add_argument("--sections", default="c2,c3,c4,c5,cases,sparse")
+    ap.add_argument("--sections", default="c2,c3,c4,c5,cases,sparse,grid")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jobs", type=int, default=4096, help="served-stream jobs")
@@ -301,6 +301,63 @@ def section_cases(stl, args):
         del x
         torch.cuda.empty_cache()
     return out
+
+
+# ---------------------------------------------------------------- the paper's benchmark grid
+# Sec. "Evaluation Setup" (Benchmarks): box and star patterns of radius 1, 3
+# and 7 on 10240^2 grids and of radius 1 on 1024^3 grids, double and float.
+# Each pattern runs one step per pass and fused (radius 1: the paper's depths
+# 3 and 7 in 2D, 3 in 3D; radius 3: 2; radius 7: none) on both paths, with
+# the model's predicted winner next to the measured one.
+GRID = ([(shape, 2, 1, T) for shape in ("box", "star") for T in (1, 3, 7)]
+        + [(shape, 2, 3, T) for shape in ("box", "star") for T in (1, 2)]
+        + [(shape, 2, 7, 1) for shape in ("box", "star")]
+        + [(shape, 3, 1, T) for shape in ("box", "star") for T in (1, 3)])
+
+
+def section_grid(stl, args):
+    import torch
+
+    import stencil_inputs as si
+
+    out = {}
+    xs = {}
+    for shape, d, r, T in GRID:
+        n = 10240 if d == 2 else 1024
+        dims = (n,) * d
+        K = (2 * r + 1) ** d if shape == "box" else 2 * d * r + 1
+        w = si.normalised_weights(K, seed=si.weight_seed(7, 100 * d + 10 * r + (shape == "box")))
+        for dt in ("f64", "f32"):
+            if (d, dt) not in xs:
+                xs.clear()
+                torch.cuda.empty_cache()
+                g = torch.Generator(device="cuda")
+                g.manual_seed(si.data_seed(7, d))
+                xs[(d, dt)] = torch.rand(dims, generator=g, device="cuda", dtype=torch.float64).to(
+                    stl.torch_dtype(dt))
+            x = xs[(d, dt)]
+            m = stl.model_predict(shape, d, r, T, dt)
+            row = dict(predicted={-1: "valu", 0: "tie", 1: "mfma"}[m["winner"]], predicted_ratio=m["ratio"])
+            for path in ("valu", "mfma"):
+                if not stl.kernel_available(path, dt, shape, d, r, T):
+                    row[path] = dict(error="no kernel fuses this depth")
+                    continue
+                v = dict(shape=shape, K=K, d=d, r=r, dtype=dt, T=T, path=path, dims=dims, steps=4 * T,
+                         boundary="periodic")
+                res = measure(stl, v, x, w, 3, 1)
+                row[path] = {k: res[k] for k in ("gst", "roofline", "predicted_gst") if k in res} or res
+            if "gst" in row.get("valu", {}) and "gst" in row.get("mfma", {}):
+                row["measured_ratio"] = row["mfma"]["gst"] / row["valu"]["gst"]
+                row["measured"] = verdict(row["measured_ratio"])
+            name = f"{shape}-{d}d{r}r-{dt}-T{T}"
+            out[name] = row
+            log(f"grid {name}: valu {row.get('valu', {}).get('gst', float('nan')):.1f}, mfma "
+                f"{row.get('mfma', {}).get('gst', float('nan')):.1f}; predicted {row['predicted']}, "
+                f"measured {row.get('measured', '-')}")
+    xs.clear()
+    torch.cuda.empty_cache()
+    rows = [r for r in out.values() if "measured" in r]
+    return dict(cases=out, agree=sum(r["predicted"] == r["measured"] for r in rows), total=len(rows))
 
 
 # ---------------------------------------------------------------- dense vs 2:4 sparse matrix units
@@ -658,7 +715,7 @@ def _sig(x, nd=3):
     return None if x is None else float(f"{float(x):.{nd}g}")
 
 
-def summaries(variants, mcheck, precision, serving, cases, sparse=None):
+def summaries(variants, mcheck, precision, serving, cases, sparse=None, grid=None):
     """One-line summaries of every section for the JSON line (the full
     per-variant detail goes to --json-out / stderr)."""
     out = {}
@@ -680,6 +737,8 @@ def summaries(variants, mcheck, precision, serving, cases, sparse=None):
     if cases:
         out["paper_cases"] = {k: [_r(c.get("valu", {}).get("gst")), _r(c.get("mfma", {}).get("gst")),
                                   c["predicted"], c.get("measured")] for k, c in cases.items()}
+    if grid:
+        out["grid_model_check"] = f"{grid['agree']}/{grid['total']}"
     if sparse:
         out["sparse"] = {k: [_r(c.get("mfma", {}).get("gst")), _r(c.get("mfma_sparse", {}).get("gst")),
                              _r(c.get("model_speedup"), 2)] for k, c in sparse.items()}
@@ -693,6 +752,8 @@ SUMMARY_KEYS = {
     "serving": "served stream: [p50 ms, p99 ms, GStencil/s] at 0.8 load; capacity_gst [served, fifo]",
     "paper_cases": "Table 3 cases at 10240^2 / 1024^3: [VALU, MFMA GStencil/s, predicted, measured]",
     "sparse": "Table 4 analogue, bf16 periodic: [dense MFMA, 2:4 sparse MFMA GStencil/s, model sparse/dense]",
+    "grid_model_check": "the paper's benchmark grid (box/star r 1,3,7 at 10240^2, r 1 at 1024^3, f64/f32, "
+                        "one-step and fused passes): predicted winner = measured / cases with both paths",
 }
 
 
@@ -754,6 +815,7 @@ def main():
     c5 = section_serving(stl, args) if "c5" in sections else None
     cases = section_cases(stl, args) if "cases" in sections else None
     sparse = section_sparse(stl, args) if "sparse" in sections else None
+    grid = section_grid(stl, args) if "grid" in sections else None
     cpu = None if args.no_cpu or not head_name else cpu_baseline(args.n, args.cpu_seconds)
     head = ok.get(head_name, {})
     roof = dict(head.get("roofline", {}))
@@ -763,7 +825,7 @@ def main():
     detail = {
         "headline": head_name, "roofline": roof or None, "cpu_baseline": cpu, "clocks": clocks,
         "variants": ok, "model_check": mcheck, "precision": c4, "serving": c5, "paper_cases": cases,
-        "sparse": sparse,
+        "sparse": sparse, "grid": grid,
         "summary_keys": SUMMARY_KEYS,
     }
     s = json.dumps(detail)
@@ -773,7 +835,7 @@ def main():
     else:
         print("# detail " + s, file=sys.stderr, flush=True)
     print(compact_line(args, head_name, head, hv, roof, cpu, clocks,
-                       summaries(ok, mcheck, c4, c5, cases, sparse)), flush=True)
+                       summaries(ok, mcheck, c4, c5, cases, sparse, grid)), flush=True)
 
 
 def headline_clocks(stl, args, hv):

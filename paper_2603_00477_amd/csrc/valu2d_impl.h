@@ -378,13 +378,15 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
 // difference).  Float64 sets up to ~48 dwords stay in scalar registers; larger
 // ones (49 float64 box weights) are pinned in vector registers, otherwise the
 // compiler spills them to vector lanes and pays a readlane per use.
-template <typename TC, int K, typename SrcT>
+// The float64 Star-2D7R set (29 weights) stays in scalar registers: pinned in
+// vector registers beside its 15 accumulator rows per stage it needs all 256.
+template <typename TC, int K, bool SCALAR64 = false, typename SrcT>
 __device__ __forceinline__ void load_weights(TC (&wk)[K], const SrcT *w)
 {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         wk[k] = w[k];
-        if constexpr (sizeof(TC) == 4 || sizeof(TC) * K > 192) asm volatile("" : "+v"(wk[k]));
+        if constexpr (sizeof(TC) == 4 || (sizeof(TC) * K > 192 && !SCALAR64)) asm volatile("" : "+v"(wk[k]));
     }
 }
 
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_kernel(
                             offsetof(Args, w));
         wk[0] = TC(0);
     } else {
-        load_weights(wk, a.w);
+        load_weights<TC, Cfg::K, SHAPE == STENCIL_STAR && R == 7>(wk, a.w);
     }
     valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, wp, band, g % a.g.nsegs, threadIdx.x & 63);
 }
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
             wp = (ConstPtr<TC>)(jobs[j].w);  // the job table is read-only in the kernel
             wk[0] = TC(0);
         } else {
-            load_weights(wk, jobs[j].w);
+            load_weights<TC, Cfg::K, SHAPE == STENCIL_STAR && R == 7>(wk, jobs[j].w);
         }
         valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, wp, band, local % g.nsegs, lane);
     }

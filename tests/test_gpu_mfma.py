@@ -48,19 +48,21 @@ def test_mfma2d(stl, shape, r, T, dt, boundary):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
+@pytest.mark.parametrize("shape", ["box", "star"])
 @pytest.mark.parametrize("r,T", [(1, 7), (7, 1)])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
-def test_mfma2d_radius7_composites(stl, r, T, dt, boundary):
-    """Composite radius 7 (the paper's Box-2D1R fused 7 deep and Box-2D7R):
-    two full passes plus a remainder pass; Dirichlet adds the fix-up band."""
+def test_mfma2d_radius7_composites(stl, shape, r, T, dt, boundary):
+    """Composite radius 7 (the paper's Box/Star-2D1R fused 7 deep and
+    Box/Star-2D7R): two full passes plus a remainder pass; Dirichlet adds the
+    fix-up band."""
     dims = (150, 217)
-    u0, u0r, t, w = case_inputs("box", 2, r, dims, dt, seed=6500 + 10 * r + T)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6500 + 10 * r + T + (shape == "star"))
     steps = 2 * T + 1
-    p = stl.Plan("box", 2, r, w, dims, T=T, dtype=dt, path="mfma", boundary=boundary, halo=0.125)
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma", boundary=boundary, halo=0.125)
     assert p.info()["path_name"] == "mfma"
     got = run_gpu(p, t, steps)
-    ref = oracle("box", 2, r, w, u0, steps, boundary, 0.125)
+    ref = oracle(shape, 2, r, w, u0, steps, boundary, 0.125)
     assert rel_inf(got, ref) <= TOL[dt]
 
 
