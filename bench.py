@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--time-steps", type=int, default=100, help="stencil steps per sweep")
     ap.add_argument("--n", type=int, default=8192, help="grid side of the headline workload")
     ap.add_argument("--only", default="", help="comma list of headline variant names to run")
-    ap.add_argument("--sections", default="c2,c3,c4,c5,cases,sparse,grid")
+    ap.add_argument("--sections", default="c2,c3,c4,c5,cases,sparse,grid,seq")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jobs", type=int, default=4096, help="served-stream jobs")
@@ -358,6 +358,49 @@ def section_grid(stl, args):
     torch.cuda.empty_cache()
     rows = [r for r in out.values() if "measured" in r]
     return dict(cases=out, agree=sum(r["predicted"] == r["measured"] for r in rows), total=len(rows))
+
+
+# ---------------------------------------------------------------- sequential vs kernel fusion on MFMA
+# Kernel fusion (the composite of T steps, redundancy alpha) against
+# sequential-step fusion (T single-step band products, alpha = 1, the halo
+# recomputed each step), both on the matrix cores, with the model's
+# executed work per point for each (C_mfma, C_mfma_seq) and its prediction.
+SEQ_CASES = ([("box", 3, T, dt, 8192, "dirichlet") for dt in ("f64", "f32") for T in (2, 4)]
+             + [("star", 3, T, dt, 8192, "dirichlet") for dt in ("f64", "f32") for T in (2, 4)]
+             + [("box", 2, 4, "bf16", 16384, "periodic")])
+
+
+def section_seq(stl, args):
+    import torch
+
+    import stencil_inputs as si
+
+    out = {}
+    xs = {}
+    for shape, r, T, dt, n, bnd in SEQ_CASES:
+        K = (2 * r + 1) ** 2 if shape == "box" else 4 * r + 1
+        w = si.normalised_weights(K, seed=si.weight_seed(2, 0 if shape == "box" else 1))
+        if (n, dt) not in xs:
+            xs.clear()
+            torch.cuda.empty_cache()
+            xs[(n, dt)] = si.round_to(si.uniform_grid((n, n), seed=si.data_seed(2, 0)), dt)[1].to("cuda")
+        x = xs[(n, dt)]
+        m = stl.model_predict(shape, 2, r, T, dt)
+        row = dict(C_kernel_fused=m["C_mfma"], C_sequential=m["C_mfma_seq"], model_gst_kernel_fused=m["gst_mfma"],
+                   model_gst_sequential=m["gst_mfma_seq"])
+        for path in ("mfma", "mfma_seq"):
+            v = dict(shape=shape, K=K, d=2, r=r, dtype=dt, T=T, path=path, dims=(n, n), steps=100,
+                     boundary=bnd)
+            res = measure(stl, v, x, w, 3, 1)
+            row[path] = res.get("gst", res.get("error"))
+        name = f"{shape}-2d{r}r-{dt}-T{T}-{n}"
+        out[name] = row
+        log(f"seq {name}: kernel-fused {row['mfma']}, sequential {row['mfma_seq']} GSt/s; model "
+            f"{row['model_gst_kernel_fused']:.0f} vs {row['model_gst_sequential']:.0f} "
+            f"(executed flop/point/pass {row['C_kernel_fused']:.0f} vs {row['C_sequential']:.0f})")
+    xs.clear()
+    torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------- dense vs 2:4 sparse matrix units
@@ -715,7 +758,7 @@ def _sig(x, nd=3):
     return None if x is None else float(f"{float(x):.{nd}g}")
 
 
-def summaries(variants, mcheck, precision, serving, cases, sparse=None, grid=None):
+def summaries(variants, mcheck, precision, serving, cases, sparse=None, grid=None, seq=None):
     """One-line summaries of every section for the JSON line (the full
     per-variant detail goes to --json-out / stderr)."""
     out = {}
@@ -739,6 +782,11 @@ def summaries(variants, mcheck, precision, serving, cases, sparse=None, grid=Non
                                   c["predicted"], c.get("measured")] for k, c in cases.items()}
     if grid:
         out["grid_model_check"] = f"{grid['agree']}/{grid['total']}"
+    if seq:
+        out["sequential"] = {k.replace("-2d", "").replace("-8192", "").replace("-16384", ""):
+                             [_r(c["mfma"]) if isinstance(c["mfma"], float) else None,
+                              _r(c["mfma_seq"]) if isinstance(c["mfma_seq"], float) else None]
+                             for k, c in seq.items()}
     if sparse:
         out["sparse"] = {k: [_r(c.get("mfma", {}).get("gst")), _r(c.get("mfma_sparse", {}).get("gst")),
                              _r(c.get("model_speedup"), 2)] for k, c in sparse.items()}
@@ -752,6 +800,8 @@ SUMMARY_KEYS = {
     "serving": "served stream: [p50 ms, p99 ms, GStencil/s] at 0.8 load; capacity_gst [served, fifo]",
     "paper_cases": "Table 3 cases at 10240^2 / 1024^3: [VALU, MFMA GStencil/s, predicted, measured]",
     "sparse": "Table 4 analogue, bf16 periodic: [dense MFMA, 2:4 sparse MFMA GStencil/s, model sparse/dense]",
+    "sequential": "MFMA [kernel fusion, sequential-step fusion] GStencil/s (100 steps; 8192^2 Dirichlet, "
+                  "bf16 16384^2 periodic)",
     "grid_model_check": "the paper's benchmark grid (box/star r 1,3,7 at 10240^2, r 1 at 1024^3, f64/f32, "
                         "one-step and fused passes): predicted winner = measured / cases with both paths",
 }
@@ -816,6 +866,7 @@ def main():
     cases = section_cases(stl, args) if "cases" in sections else None
     sparse = section_sparse(stl, args) if "sparse" in sections else None
     grid = section_grid(stl, args) if "grid" in sections else None
+    seq = section_seq(stl, args) if "seq" in sections else None
     cpu = None if args.no_cpu or not head_name else cpu_baseline(args.n, args.cpu_seconds)
     head = ok.get(head_name, {})
     roof = dict(head.get("roofline", {}))
@@ -825,7 +876,7 @@ def main():
     detail = {
         "headline": head_name, "roofline": roof or None, "cpu_baseline": cpu, "clocks": clocks,
         "variants": ok, "model_check": mcheck, "precision": c4, "serving": c5, "paper_cases": cases,
-        "sparse": sparse, "grid": grid,
+        "sparse": sparse, "grid": grid, "sequential": seq,
         "summary_keys": SUMMARY_KEYS,
     }
     s = json.dumps(detail)
@@ -835,7 +886,7 @@ def main():
     else:
         print("# detail " + s, file=sys.stderr, flush=True)
     print(compact_line(args, head_name, head, hv, roof, cpu, clocks,
-                       summaries(ok, mcheck, c4, c5, cases, sparse, grid)), flush=True)
+                       summaries(ok, mcheck, c4, c5, cases, sparse, grid, seq)), flush=True)
 
 
 def headline_clocks(stl, args, hv):

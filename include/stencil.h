@@ -62,11 +62,18 @@ enum stencil_boundary { STENCIL_DIRICHLET = 0, STENCIL_PERIODIC = 1 };
  * Sparse Hardware"): bf16/f16 storage, d = 2, composite radius r*T <= 7; one
  * instruction covers two kernel columns of the band layout.  Never chosen by
  * STENCIL_PATH_AUTO; the autotuner may pick it. */
+/* STENCIL_PATH_MFMA_SEQ: the matrix cores with sequential-step fusion: T
+ * single-step band products per pass with the intermediate fields in LDS
+ * (alpha = 1, halo recomputed per step; Sec. "Handling Stencils with Small
+ * Radius" contrasts the two fusions); d = 2, r <= 3, T <= 4, every dtype but
+ * the compensated one; exact on Dirichlet grids without a band fix-up.
+ * Never chosen by STENCIL_PATH_AUTO. */
 enum stencil_path {
     STENCIL_PATH_AUTO = 0,
     STENCIL_PATH_VALU = 1,
     STENCIL_PATH_MFMA = 2,
-    STENCIL_PATH_MFMA_SPARSE = 3
+    STENCIL_PATH_MFMA_SPARSE = 3,
+    STENCIL_PATH_MFMA_SEQ = 4
 };
 
 enum stencil_status {
@@ -93,7 +100,7 @@ typedef struct stencil_plan_s *stencil_plan_t;
 /* Read-only description of a plan. */
 typedef struct {
     int shape, d, r, T, dtype, boundary;
-    int path;          /* resolved path: STENCIL_PATH_VALU, _MFMA or _MFMA_SPARSE */
+    int path;          /* resolved path: STENCIL_PATH_VALU, _MFMA, _MFMA_SPARSE or _MFMA_SEQ */
     int64_t dims[3];
     int K;             /* points of the single-step pattern                   */
     int K_T;           /* non-zero points of the T-step composite kernel      */
@@ -261,6 +268,16 @@ typedef struct {
     int scenario;        /* 1 MB->MB, 2 MB->CB, 3 CB->MB, 4 CB->CB            */
     int sweet_spot;      /* alpha*gamma < S PP_mfma / PP_valu                 */
     int winner;          /* -1 VALU, 0 tie (ratio in [0.87, 1.15]), +1 MFMA    */
+    /* Halo terms of this library's tilings (the paper's model omits halos and
+     * attributes measured excess work to their recomputation):              */
+    double halo_valu;    /* executed / useful VALU FMAs: the skirt of r*T points
+                            each fused tile recomputes (1 for one-step passes
+                            whose halo is staged)                             */
+    double C_mfma_seq;   /* executed flops per point per pass of sequential-step
+                            MFMA fusion (alpha = 1): T single-step band
+                            products over step regions widened by the halo and
+                            rounded up to 16 x 16 tiles (d = 2; 0 otherwise)  */
+    double gst_mfma_seq; /* its GStencil/s on the roofline (0 when d = 3)     */
 } stencil_model_out_t;
 
 /*

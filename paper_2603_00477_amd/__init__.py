@@ -13,13 +13,14 @@ import numpy as np
 
 from . import _abi
 from ._abi import (BF16, BOX, DIRICHLET, F16, F32, F32_BF16X3, F64, PATH_AUTO, PATH_MFMA,
-                   PATH_MFMA_SPARSE, PATH_VALU, PERIODIC, STAR, StencilError, check, lib)
+                   PATH_MFMA_SEQ, PATH_MFMA_SPARSE, PATH_VALU, PERIODIC, STAR, StencilError, check, lib)
 
 SHAPES = {"star": STAR, "box": BOX}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16, "bf16x3": F32_BF16X3}
 BOUNDARIES = {"dirichlet": DIRICHLET, "periodic": PERIODIC}
-PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA, "mfma_sparse": PATH_MFMA_SPARSE}
-PATH_NAMES = {PATH_VALU: "valu", PATH_MFMA: "mfma", PATH_MFMA_SPARSE: "mfma_sparse"}
+PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA, "mfma_sparse": PATH_MFMA_SPARSE,
+         "mfma_seq": PATH_MFMA_SEQ}
+PATH_NAMES = {PATH_VALU: "valu", PATH_MFMA: "mfma", PATH_MFMA_SPARSE: "mfma_sparse", PATH_MFMA_SEQ: "mfma_seq"}
 
 
 def _code(table, v):

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libstencil_mi355.so")
 STAR, BOX = 0, 1
 F64, F32, BF16, F16, F32_BF16X3 = 0, 1, 2, 3, 4
 DIRICHLET, PERIODIC = 0, 1
-PATH_AUTO, PATH_VALU, PATH_MFMA, PATH_MFMA_SPARSE = 0, 1, 2, 3
+PATH_AUTO, PATH_VALU, PATH_MFMA, PATH_MFMA_SPARSE, PATH_MFMA_SEQ = 0, 1, 2, 3, 4
 OPT_PATH, OPT_HALO_VALUE, OPT_TILE_ROWS, OPT_T = 1, 2, 3, 4
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "ALIAS", 4: "OOM", 5: "HIP"}
 
@@ -57,7 +57,9 @@ class ModelOut(ctypes.Structure):
                 ("P_valu", ctypes.c_double), ("P_mfma_raw", ctypes.c_double),
                 ("P_mfma", ctypes.c_double), ("gst_valu", ctypes.c_double),
                 ("gst_mfma", ctypes.c_double), ("ratio", ctypes.c_double),
-                ("scenario", ctypes.c_int), ("sweet_spot", ctypes.c_int), ("winner", ctypes.c_int)]
+                ("scenario", ctypes.c_int), ("sweet_spot", ctypes.c_int), ("winner", ctypes.c_int),
+                ("halo_valu", ctypes.c_double), ("C_mfma_seq", ctypes.c_double),
+                ("gst_mfma_seq", ctypes.c_double)]
 
 
 _lib = None

@@ -89,7 +89,7 @@ hipError_t stage_job_table(BatchStaging *stage, const void *jobs, size_t job_byt
 
 // One launchable kernel variant.
 struct KernelEntry {
-    int path;    // STENCIL_PATH_VALU, STENCIL_PATH_MFMA or STENCIL_PATH_MFMA_SPARSE
+    int path;    // STENCIL_PATH_VALU or one of the MFMA paths
     int dtype;
     int shape;   // -1 = any
     int d;
@@ -118,6 +118,7 @@ const std::vector<KernelEntry> &mfma2d_table_bf16();
 const std::vector<KernelEntry> &mfma2d_table_f16();
 const std::vector<KernelEntry> &mfma2d_table_x3();
 const std::vector<KernelEntry> &mfma2d_table_sparse();  // 2:4 structured-sparse instructions
+const std::vector<KernelEntry> &mfma2d_table_seq();     // sequential-step fusion
 const std::vector<KernelEntry> &mfma3d_table_f64();
 const std::vector<KernelEntry> &mfma3d_table_f32();
 std::vector<const std::vector<KernelEntry> *> all_kernel_tables();
@@ -134,8 +135,14 @@ struct MfmaLayout {
 };
 MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype);
 
-// MFMA-family paths (operand fragments, kernel fusion, Dirichlet band fix-up).
-inline bool is_mfma_path(int path) { return path == STENCIL_PATH_MFMA || path == STENCIL_PATH_MFMA_SPARSE; }
+// MFMA-family paths (operand fragments on the device).
+inline bool is_mfma_path(int path)
+{
+    return path == STENCIL_PATH_MFMA || path == STENCIL_PATH_MFMA_SPARSE || path == STENCIL_PATH_MFMA_SEQ;
+}
+// Paths that apply the T-step composite kernel (exact on Dirichlet grids only
+// at distance >= r (T - 1) from the boundary: the band is redone by VALU steps).
+inline bool is_kernel_fused_path(int path) { return path == STENCIL_PATH_MFMA || path == STENCIL_PATH_MFMA_SPARSE; }
 
 // Operands of the 2:4 sparse layout (d = 2, 16-bit): per column pair, 64
 // lanes x 8 compressed weights, then 64 lanes x one int32 of positions.

@@ -95,6 +95,66 @@ __host__ __device__ constexpr int sparse_pairs(int shape, int r, int t) { return
 // Row of the 32-row data block held at position e (0..3) of group h (0..7).
 __host__ __device__ constexpr int sparse_group_row(int h, int e) { return 2 * h + (e & 1) + 16 * (e >> 1); }
 
+// Sequential-step fusion (d = 2): step s (1..t) of a pass computes frame
+// rows and columns [seq_start, seq_start + seq_size) of a tile x tile output
+// tile's frame (the input block with its halo of r t points on each side):
+// the points later steps need, [r s, tile + 2 r t - r s), widened to whole
+// 16 x 16 MFMA tiles; with 32-row operand blocks (16-bit) a block starts at
+// a row = r (mod 8) so that its 8-row operand chunks are 16-byte aligned.
+__host__ __device__ constexpr int seq_start(int r, int s, int kdim) { return kdim == 32 ? r + 8 * ((r * (s - 1)) / 8) : r * s; }
+__host__ __device__ constexpr int seq_size(int tile, int r, int t, int s, int kdim)
+{
+    return ((tile + 2 * r * t - r * s - seq_start(r, s, kdim) + 15) / 16) * 16;
+}
+__host__ __device__ constexpr int seq_kp(int r, int kdim) { return ((16 + 2 * r + kdim - 1) / kdim) * kdim; }
+// Frame extent holding every operand read: step s reads rows f0 - r ..
+// f0 - r + kp - 1 and columns g0 - r .. g0 + 15 + r of its blocks.
+__host__ __device__ constexpr int seq_frame_rows(int tile, int r, int t, int kdim)
+{
+    int m = tile + 2 * r * t;
+    for (int s = 1; s <= t; ++s) {
+        const int e = seq_start(r, s, kdim) + seq_size(tile, r, t, s, kdim) - 16 - r + seq_kp(r, kdim);
+        m = m > e ? m : e;
+    }
+    return m;
+}
+__host__ __device__ constexpr int seq_frame_cols(int tile, int r, int t, int kdim)
+{
+    int m = tile + 2 * r * t;
+    for (int s = 1; s <= t; ++s) {
+        const int e = seq_start(r, s, kdim) + seq_size(tile, r, t, s, kdim) + r;
+        m = m > e ? m : e;
+    }
+    return m;
+}
+// Row pitch (row-major frames, 4-deep operands) and column pitch
+// (column-major frames, 32-deep operands: an odd number of 16-byte units).
+__host__ __device__ constexpr int seq_pitch(int tile, int r, int t, int kdim)
+{
+    if (kdim == 32) {
+        const int u = (seq_frame_rows(tile, r, t, kdim) + 7) / 8;
+        return (u % 2 ? u : u + 1) * 8;
+    }
+    const int c = seq_frame_cols(tile, r, t, kdim);
+    return c + (c % 32 == 0 ? 1 : 0);
+}
+__host__ __device__ constexpr int seq_frame_elems(int tile, int r, int t, int kdim)
+{
+    return kdim == 32 ? seq_frame_cols(tile, r, t, kdim) * seq_pitch(tile, r, t, kdim)
+                      : seq_frame_rows(tile, r, t, kdim) * seq_pitch(tile, r, t, kdim);
+}
+// LDS bytes: two frames plus the single step's operand fragments.
+__host__ __device__ constexpr int seq_lds_bytes(int shape, int tile, int r, int t, int kdim, int elem_bytes)
+{
+    return 2 * seq_frame_elems(tile, r, t, kdim) * elem_bytes +
+           band_total_frags(shape, r, 1, kdim, 2) * 64 * (kdim / 4) * elem_bytes;
+}
+// 64 x 64 output tiles, or 32 x 32 where two 64-tile frames would not fit.
+__host__ __device__ constexpr int seq_tile(int shape, int r, int t, int kdim, int elem_bytes)
+{
+    return seq_lds_bytes(shape, 64, r, t, kdim, elem_bytes) <= 150 * 1024 ? 64 : 32;
+}
+
 // k of the MFMA instruction for a storage dtype (STENCIL_* codes).
 __host__ __device__ constexpr int mfma_kdim(int dtype) { return dtype <= 1 ? 4 : 32; }
 

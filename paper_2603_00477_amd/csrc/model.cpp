@@ -85,6 +85,47 @@ MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype)
     return L;
 }
 
+// Skirt recomputation of the VALU kernels' fused tiles: executed / useful
+// FMAs.  2D: a wave's band of 64 W columns (W = 16-byte vector) keeps
+// 64 W - 2 E outputs, E = r T rounded up to W.  3D: an in-plane tile of
+// (TY WY) x (TX W) points keeps (TY WY - 2 EY) x (TX W - 2 EX), EY = r T for
+// fused passes (one-step passes stage their halo: no skirt); the thread tiles
+// are those the 3D launcher picks.
+static double valu_halo_factor(int d, int r, int T, int dtype)
+{
+    const int D = dtype_bytes(dtype);
+    const int W = 16 / D > 8 ? 8 : 16 / D;
+    if (d == 2) {
+        const int E = (r * T + W - 1) / W * W;
+        return (64.0 * W) / (64.0 * W - 2.0 * E);
+    }
+    if (T == 1) return 1.0;
+    const int WY = r * T >= 6 ? (r >= 3 ? 2 : 1) : 2;
+    const int TX = 16, TY = r * T >= 6 ? 32 / WY : 16;
+    const int EY = r * T, EX = (EY + W - 1) / W * W;
+    const double PY = TY * WY, PX = TX * W;
+    if (PY <= 2 * EY || PX <= 2 * EX) return 0.0;
+    return PY * PX / ((PY - 2.0 * EY) * (PX - 2.0 * EX));
+}
+
+// Executed flops per point per pass of sequential-step MFMA fusion: each of
+// the T steps runs the single step's band product (every structurally
+// non-zero k-block of every column) on (size(s) / 16)^2 16 x 16 tiles of a
+// tile x tile output tile.
+static double mfma_seq_flops(int shape, int r, int T, int dtype)
+{
+    const int kdim = mfma_k(dtype);
+    const int eb = dtype == STENCIL_F64 ? 8 : (dtype == STENCIL_F32 ? 4 : 2);
+    const int tile = seq_tile(shape, r, T, kdim, eb);
+    const double per_block = 2.0 * 16 * 16 * kdim * band_total_frags(shape, r, 1, kdim, 2);
+    double blocks = 0;
+    for (int s = 1; s <= T; ++s) {
+        const double nb = seq_size(tile, r, T, s, kdim) / 16;
+        blocks += nb * nb;
+    }
+    return blocks * per_block / ((double)tile * tile);
+}
+
 }  // namespace stl
 
 using namespace stl;
@@ -180,6 +221,13 @@ extern "C" int stencil_model_predict(const stencil_model_in_t *in, const stencil
     o.scenario = !cu_cb ? (!tc_cb ? 1 : 2) : (!tc_cb ? 3 : 4);
     o.sweet_spot = o.gamma * o.alpha < o.S * PPm / H.PP_valu;
     o.winner = o.ratio < 0.87 ? -1 : (o.ratio > 1.15 ? 1 : 0);
+    o.halo_valu = valu_halo_factor(in->d, in->r, T, in->dtype);
+    if (in->d == 2 && in->dtype != STENCIL_F32_BF16X3) {
+        o.C_mfma_seq = mfma_seq_flops(in->shape, in->r, T, in->dtype);
+        const double useful = o.C_valu;  // 2 K T per point per pass
+        const double P_raw = std::fmin(H.PP_mfma, H.BB * o.C_mfma_seq / o.M);
+        o.gst_mfma_seq = P_raw * useful / o.C_mfma_seq / (2.0 * o.K) / 1e9;
+    }
     *out = o;
     return STENCIL_OK;
 }

@@ -186,6 +186,7 @@ int resolve_path(stencil_plan_s *p)
     const bool v = has_path(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, p->T);
     const bool m_built = has_path(STENCIL_PATH_MFMA, p->dtype, p->shape, p->d, p->r, p->T);
     const bool sp_built = has_path(STENCIL_PATH_MFMA_SPARSE, p->dtype, p->shape, p->d, p->r, p->T);
+    const bool seq_built = has_path(STENCIL_PATH_MFMA_SEQ, p->dtype, p->shape, p->d, p->r, p->T);
     // a kernel-fused Dirichlet pass needs a VALU kernel of the same depth for
     // its boundary band (launch_fixup)
     const bool band_ok = p->boundary == STENCIL_PERIODIC || p->T == 1 ||
@@ -205,13 +206,16 @@ int resolve_path(stencil_plan_s *p)
     if (path == STENCIL_PATH_MFMA_SPARSE && !sp_built)
         return fail(STENCIL_ERR_UNSUPPORTED,
                     "2:4 sparse MFMA path not built for this dtype/shape/d/r/T (bf16/f16, d = 2, r*T <= 7)");
-    if (is_mfma_path(path) && !band_ok)
+    if (path == STENCIL_PATH_MFMA_SEQ && !seq_built)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "sequential-step MFMA path not built for this dtype/shape/d/r/T (d = 2, r <= 3, T <= 4)");
+    if (is_kernel_fused_path(path) && !band_ok)
         return fail(STENCIL_ERR_UNSUPPORTED,
                     "Dirichlet MFMA plan needs a fused VALU kernel of the same T for its boundary band; "
                     "use a periodic boundary or another T");
     if (p->dtype == STENCIL_F32_BF16X3 && path != STENCIL_PATH_MFMA)
         return fail(STENCIL_ERR_UNSUPPORTED, "bf16x3 is an MFMA-only mode");
-    if (is_mfma_path(path) && p->boundary == STENCIL_PERIODIC)
+    if (is_kernel_fused_path(path) && p->boundary == STENCIL_PERIODIC)
         for (int i = 0; i < p->d; ++i)
             if (p->dims[i] < 2 * (int64_t)p->r * p->T + 1)
                 return fail(STENCIL_ERR_INVALID_ARG,
@@ -244,6 +248,8 @@ void build_fragments(const stencil_plan_s *p, int t, std::vector<uint8_t> *hi, s
     if (!find_kernel(p->path, p->dtype, p->shape, p->d, p->r, t)) return;
     if (p->path == STENCIL_PATH_MFMA_SPARSE)
         mfma_build_sparse_fragments(p->shape, p->r, p->w.data(), t, p->dtype, hi);
+    else if (p->path == STENCIL_PATH_MFMA_SEQ)  // the single step's band, whatever the depth
+        mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), 1, p->dtype, hi, lo);
     else
         mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), t, p->dtype, hi, lo);
 }
@@ -341,7 +347,7 @@ std::vector<PassDesc> schedule(const stencil_plan_s *p, int64_t steps)
             path = STENCIL_PATH_VALU;
         }
         if (k) {
-            const bool fix = is_mfma_path(path) && p->boundary == STENCIL_DIRICHLET && t > 1;
+            const bool fix = is_kernel_fused_path(path) && p->boundary == STENCIL_DIRICHLET && t > 1;
             out.push_back({path, t, k, fix});
         } else {
             const KernelEntry *k1 = find_kernel(STENCIL_PATH_VALU, p->dtype, p->shape, p->d, p->r, 1);
@@ -677,7 +683,7 @@ extern "C" int stencil_plan_set(stencil_plan_t p, int option, double value)
         if ((double)v != value) return fail(STENCIL_ERR_INVALID_ARG, "integer option expected");
         const int old_req = p->path_req, old_path = p->path, old_T = p->T;
         if (option == STENCIL_OPT_PATH) {
-            if (v < STENCIL_PATH_AUTO || v > STENCIL_PATH_MFMA_SPARSE)
+            if (v < STENCIL_PATH_AUTO || v > STENCIL_PATH_MFMA_SEQ)
                 return fail(STENCIL_ERR_INVALID_ARG, "unknown path");
             p->path_req = v;
         } else {

@@ -118,6 +118,7 @@ std::vector<const std::vector<KernelEntry> *> all_kernel_tables()
             &valu2d_table_x3(),    &valu3d_kernels(),    &valu3d_box_kernels(), &valu2d_table_cases(),
             &mfma2d_table_cases(), &mfma3d_table_cases(), &mfma2d_table_f64(),  &mfma2d_table_f32(),
             &mfma2d_table_bf16(),  &mfma2d_table_f16(),  &mfma2d_table_x3(),    &mfma3d_table_f64(),
-            &mfma3d_table_f32(),   &mfma2d_table_sparse(), &generic_kernels()};
+            &mfma3d_table_f32(),   &mfma2d_table_sparse(), &mfma2d_table_seq(),
+            &generic_kernels()};
 }
 }  // namespace stl

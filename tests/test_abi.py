@@ -202,3 +202,21 @@ def test_sparse_path_model_and_availability():
     assert q.info()["S"] == pytest.approx(169 / 448)
     q.set(stl._abi.OPT_PATH, stl.PATH_MFMA)
     assert q.info()["path_name"] == "mfma" and q.info()["S"] == pytest.approx(169 / 416)
+
+
+def test_halo_model_terms():
+    # float64 Box-2D3R fused 2 deep on 64 x 64 tiles: step 1 covers 80 x 80
+    # (the needed 70 x 70 rounded up to 16-point tiles), step 2 64 x 64; each
+    # 16 x 16 tile issues 7 columns x 6 four-deep k-blocks of 2*16*16*4 flops
+    m = stl.model_predict("box", 2, 3, 2, "f64")
+    assert m["C_mfma_seq"] == pytest.approx((25 + 16) * 7 * 6 * 2 * 16 * 16 * 4 / 4096)
+    # it issues more than the kernel-fused layout (alpha / S = 1.72 / 0.464)
+    assert m["C_mfma_seq"] > m["C_mfma"] and m["gst_mfma_seq"] < m["gst_mfma"]
+    # VALU skirt: float64 bands of 128 columns keep 128 - 2*6
+    assert m["halo_valu"] == pytest.approx(128 / 116)
+    # (the skirt rounds up to whole 16-byte vectors: 3 -> 4 columns)
+    assert stl.model_predict("box", 2, 3, 1, "f64")["halo_valu"] == pytest.approx(128 / 120)
+    # 3D one-step passes stage their halo: no skirt
+    assert stl.model_predict("star", 3, 2, 1, "f32")["halo_valu"] == 1.0
+    assert stl.model_predict("star", 3, 2, 2, "f32")["halo_valu"] > 1.3
+    assert stl.kernel_available("mfma_seq", "bf16", "box", 2, 2, 4)

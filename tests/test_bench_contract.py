@@ -141,7 +141,10 @@ def test_json_line_is_small_and_complete():
     sparse = {f"box-2d{r}r-bf16-T{T}-{n}": {"mfma": {"gst": 1234.567}, "mfma_sparse": {"gst": 1534.567},
                                             "model_speedup": 1.25} for r, T, n in ((1, 7, 10240), (2, 3, 16384),
                                                                                    (3, 2, 8192), (3, 2, 8193))}
-    summ = bench.summaries(variants, mcheck, precision, serving, cases, sparse)
+    seq = {f"{sh}-2d3r-{dt}-T{T}-8192": {"mfma": 123.456, "mfma_seq": 111.111} for sh in ("box", "star")
+           for dt in ("f64", "f32") for T in (2, 4)}
+    grid = {"agree": 32, "total": 32}
+    summ = bench.summaries(variants, mcheck, precision, serving, cases, sparse, grid, seq)
     s = bench.compact_line(args, head_name, variants[head_name], hv, roof, cpu, clocks, summ)
     assert len(s.encode()) <= 4096, len(s)
     line = json.loads(s)

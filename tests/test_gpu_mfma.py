@@ -210,3 +210,52 @@ def test_mfma2d_sparse_refusals(stl):
             stl.Plan("box", 2, r, np.full((2 * r + 1) ** 2, 1.0 / (2 * r + 1) ** 2), (64, 64), T=T, dtype=dt,
                      path="mfma_sparse", boundary="periodic")
         assert e.value.status == "UNSUPPORTED"
+
+
+SEQ_CASES = [(shape, r, T) for shape in ("box", "star") for r, T in ((1, 1), (1, 4), (2, 2), (2, 3), (3, 2), (3, 4))]
+
+
+@pytest.mark.parametrize("shape,r,T", SEQ_CASES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+def test_mfma2d_sequential(stl, shape, r, T, dt, boundary):
+    """Sequential-step fusion on the matrix cores (T single-step band products
+    per pass, intermediates in LDS): the oracle within 1e-12 / 1e-5 over two
+    passes and a remainder, Dirichlet with a non-zero halo value and no
+    boundary-band fix-up, on grids with ragged 64-point tiles."""
+    dims = (150, 217)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6850 + 10 * r + T)
+    steps = 2 * T + 1
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma_seq", boundary=boundary, halo=0.125)
+    assert p.info()["path_name"] == "mfma_seq"
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0, steps, boundary, 0.125)
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("shape,r,T", [("box", 2, 4), ("star", 3, 2), ("box", 1, 3)])
+def test_mfma2d_sequential_low_precision(stl, dt, shape, r, T):
+    """16-bit sequential fusion: every step rounds its result to the storage
+    type, so the bound counts steps rather than passes (single-step weights
+    rounded once, K float32 accumulations per step)."""
+    dims = (160, 300)
+    u0, u0r, t, w = case_inputs(shape, 2, r, dims, dt, seed=6870 + 10 * r + T)
+    steps = 2 * T + 1
+    p = stl.Plan(shape, 2, r, w, dims, T=T, dtype=dt, path="mfma_seq", boundary="periodic")
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 2, r, w, u0r, steps, "periodic")
+    err = float(np.max(np.abs(got - ref)))
+    K = omodel.K_points(shape, 2, r)
+    assert err <= lowp_bound(dt, K, steps, float(np.max(np.abs(u0r)))), err
+
+
+@pytest.mark.parametrize("dims", [(5, 7), (9, 70), (64, 64), (65, 129)])
+def test_mfma2d_sequential_small_periodic(stl, dims):
+    """Periodic grids smaller than the tile and its halo (the staged block
+    wraps several times)."""
+    u0, u0r, t, w = case_inputs("box", 2, 2, dims, "f64", seed=6890)
+    p = stl.Plan("box", 2, 2, w, dims, T=3, dtype="f64", path="mfma_seq", boundary="periodic")
+    got = run_gpu(p, t, 7)
+    ref = oracle("box", 2, 2, w, u0, 7, "periodic")
+    assert rel_inf(got, ref) <= 1e-12
