@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/stencil.h"
+#include "mfma_layout.h"
 
 namespace stl {
 
@@ -148,6 +149,18 @@ inline bool is_kernel_fused_path(int path) { return path == STENCIL_PATH_MFMA ||
 // lanes x 8 compressed weights, then 64 lanes x one int32 of positions.
 void mfma_build_sparse_fragments(int shape, int r, const double *w, int steps, int dtype,
                                  std::vector<uint8_t> *out);
+
+// Operands of the 16-bit row layout (d = 2; see mfma_layout.h): per
+// non-empty k-block of each composite row, 64 lanes x 8 weights.
+void mfma_build_row_fragments(int shape, int r, const double *w, int steps, int dtype,
+                              std::vector<uint8_t> *out);
+// Whether a dense MFMA pass of t steps uses the row layout: 16-bit operands,
+// d = 2, and an operand table that fits LDS (24 fragments; larger composites
+// keep the column layout, whose table is read per column).
+inline bool mfma_row_layout(int dtype, int d, int shape, int r, int t)
+{
+    return d == 2 && (dtype == STENCIL_BF16 || dtype == STENCIL_F16) && rows_total_frags(shape, r, t) <= 24;
+}
 
 // Build the lane-ordered operand fragments of the composite on the host.
 // `hi`/`lo` receive raw element bytes in the MFMA operand type.

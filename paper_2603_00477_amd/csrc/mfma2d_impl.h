@@ -575,12 +575,174 @@ __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
     }
 }
 
+// 16-bit operands, row layout (mfma_layout.h): one 16V x 16NW output tile.
+// The input block is staged row-major (16-byte loads and LDS writes, no
+// transposition); for every composite row a and k-block the wave issues one
+// MFMA per stacked tile with the weight band as operand A and 8 consecutive
+// columns of one data row per lane as operand B; the transposed 16 x 16
+// results give each lane 4 consecutive output columns of one row.
+template <int DT, int SHAPE, int r, int T, int V, int NW>
+__device__ __forceinline__ void mfma2d_rows_tile(const Mfma2DArgs &a, const int tile)
+{
+    using MT = MfmaTypes<DT>;
+    using TS = typename MT::TS;
+    using OP = typename MT::OP;
+    using FR = typename MT::FR;
+    using ACC = typename MT::ACC;
+    static_assert(MT::KDIM == 32 && !MT::X3, "16-bit operands");
+    constexpr int R = r * T, DL = rows_delta(R);
+    constexpr int TR = 16 * V, TC = 16 * NW, NT = 64 * NW;
+    constexpr int LRD = TR + 2 * R;                                  // frame rows
+    constexpr int NKB0 = rows_nblk(SHAPE, r, T, 0) + rows_kk_lo(SHAPE, r, T, 0);  // widest row's k extent
+    constexpr int KMAX = 16 * (NW - 1) + 32 * NKB0;                  // frame columns read
+    constexpr int LCD = TC + 2 * R + DL;                             // frame columns holding data
+    constexpr int LCF = ((KMAX > LCD ? KMAX : LCD) + 7) / 8 * 8;     // staged columns
+    constexpr int PIT = (LCF / 8) % 2 ? LCF : LCF + 8;               // odd number of 16-byte units per row
+    constexpr int NFRAG = rows_total_frags(SHAPE, r, T);
+    constexpr bool ALDS = NFRAG <= 24;
+
+    __shared__ __attribute__((aligned(16))) OP lb[LRD * PIT];
+    __shared__ __attribute__((aligned(16))) FR lA[ALDS ? NFRAG * 64 : 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lg = lane >> 4, ln = lane & 15;
+    const int r0 = (tile / a.ntc) * TR, c0 = (tile % a.ntc) * TC;
+    const int n0 = a.n0, n1 = a.n1;
+    const bool periodic = a.periodic != 0;
+    const TS *src = static_cast<const TS *>(a.src);
+    const FR *afr = static_cast<const FR *>(a.afrag);
+    const int fr0 = r0 - R, fc0 = c0 - R - DL;  // frame origin in the grid (fc0 = 0 mod 8)
+
+    // A table: loads in flight during the staging
+    constexpr int NAT = ALDS ? (NFRAG * 64 + NT - 1) / NT : 1;
+    FR ta[NAT];
+    if constexpr (ALDS) {
+#pragma unroll
+        for (int i = 0; i < NAT; ++i) {
+            const int e = tid + i * NT;
+            if (e < NFRAG * 64) ta[i] = afr[e];
+        }
+    }
+    // ---- stage the frame: interior tiles in 16-byte chunks (8 elements)
+    constexpr int NCH = LCF / 8;
+    const bool fast = fr0 >= 0 && fr0 + LRD <= n0 && fc0 >= 0 && fc0 + LCF <= n1 && (n1 % 8) == 0 &&
+                      (reinterpret_cast<uintptr_t>(src) % 16) == 0;
+    if (fast) {
+        constexpr int NE = (LRD * NCH + NT - 1) / NT;
+        constexpr int CB = NE < 8 ? NE : 8;
+#pragma unroll
+        for (int e0 = 0; e0 < NE; e0 += CB) {
+            uint4 v[CB];
+#pragma unroll
+            for (int i = 0; i < CB; ++i) {
+                const int e = tid + (e0 + i) * NT;
+                const int row = e / NCH, ch = e - row * NCH;
+                // clamped index: every lane loads (in bounds), so the loads
+                // of a batch stay in registers and in flight together
+                const int ec = e < LRD * NCH ? e : LRD * NCH - 1;
+                const int rowc = ec / NCH, chc = ec - rowc * NCH;
+                (void)row;
+                (void)ch;
+                v[i] = *reinterpret_cast<const uint4 *>(src + (int64_t)(fr0 + rowc) * n1 + fc0 + 8 * chc);
+            }
+#pragma unroll
+            for (int i = 0; i < CB; ++i) {
+                const int e = tid + (e0 + i) * NT;
+                const int row = e / NCH, ch = e - row * NCH;
+                if (e0 + i < NE && e < LRD * NCH) *reinterpret_cast<uint4 *>(&lb[row * PIT + 8 * ch]) = v[i];
+            }
+        }
+    } else {
+        // edge tiles: element by element with the boundary rule; columns past
+        // the data (read only against zero weights) get zeros
+        for (int e = tid; e < LRD * LCF; e += NT) {
+            const int row = e / LCF, col = e - row * LCF;
+            int gr = fr0 + row, gc = fc0 + col;
+            OP v = OP(0);
+            if (col < LCD) {
+                const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
+                v = to_op<OP>(a.h);
+                if (in || periodic) {
+                    gr = wrap(gr, n0);
+                    gc = wrap(gc, n1);
+                    v = to_op<OP>(load_val(src[(int64_t)gr * n1 + gc]));
+                }
+            }
+            lb[row * PIT + col] = v;
+        }
+    }
+    if constexpr (ALDS) {
+#pragma unroll
+        for (int i = 0; i < NAT; ++i) {
+            const int e = tid + i * NT;
+            if (e < NFRAG * 64) lA[e] = ta[i];
+        }
+    }
+    __syncthreads();
+
+    ACC acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = ACC{};
+    const int colw = 16 * wave + 8 * lg;
+#pragma unroll
+    for (int ar = -R; ar <= R; ++ar) {
+        if (band_amax(SHAPE, r, T, 0, ar) < 0) continue;
+        const int klo = rows_kk_lo(SHAPE, r, T, ar), nb = rows_nblk(SHAPE, r, T, ar);
+        const int off = rows_frag_offset(SHAPE, r, T, ar);
+#pragma unroll
+        for (int ib = 0; ib < nb; ++ib) {
+            const FR A = ALDS ? lA[(off + ib) * 64 + lane] : afr[(off + ib) * 64 + lane];
+            const int col = colw + 32 * (klo + ib);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const FR B = *reinterpret_cast<const FR *>(&lb[(16 * v + ln + ar + R) * PIT + col]);
+                acc[v] = mfma16(A, B, acc[v]);
+            }
+        }
+    }
+
+    // ---- store: lane (lg, ln) holds row r0 + 16 v + ln, columns 4 lg .. 4 lg + 3
+    TS *dst = static_cast<TS *>(a.dst);
+    const int gc = c0 + 16 * wave + 4 * lg;
+    const bool vec = gc + 4 <= n1 && (n1 % 4) == 0 && (reinterpret_cast<uintptr_t>(dst) % 8) == 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int gr = r0 + 16 * v + ln;
+        if (gr >= n0 || gc >= n1) continue;
+        TS *p = dst + (int64_t)gr * n1 + gc;
+        if (vec) {
+            RawVec<TS, 4> ov;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ov.e[e] = to_storage<TS>(acc[v][e]);
+            ov.store(p);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (gc + e < n1) p[e] = to_storage<TS>(acc[v][e]);
+        }
+    }
+}
+
+// The 16-bit dense kernels use the row layout when its operand table fits
+// LDS (measured on 16384^2 against the column layout: Box-2D2R bf16 T = 4
+// +5 %, T = 1 +2 %; Box-2D3R bf16 T = 4, 50 fragments read from L2, -41 %);
+// float64/float32, the compensated mode and the sparse instructions use the
+// column layout.  Must agree with mfma_row_layout() (operand upload).
+template <int DT, int SHAPE, int r, int T, bool SP>
+constexpr bool use_rows()
+{
+    return MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3 && !SP && rows_total_frags(SHAPE, r, T) <= 24;
+}
+
 template <int DT, int SHAPE, int r, int T, int V, int NW, bool SP>
 __global__ __launch_bounds__(64 * NW) void mfma2d_kernel(Mfma2DArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= a.ntiles) return;
-    mfma2d_tile<DT, SHAPE, r, T, V, NW, SP>(a, tile);
+    if constexpr (use_rows<DT, SHAPE, r, T, SP>())
+        mfma2d_rows_tile<DT, SHAPE, r, T, V, NW>(a, tile);
+    else
+        mfma2d_tile<DT, SHAPE, r, T, V, NW, SP>(a, tile);
 }
 
 // Persistent batched launch over the tiles of several jobs: workgroup b takes
@@ -596,7 +758,10 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs 
     for (int item = xcd_remap(blockIdx.x, gridDim.x); item < total; item += gridDim.x) {
         while (j + 1 < njobs && tile_start[j + 1] <= item) ++j;
         const Mfma2DArgs a = jobs[j];
-        mfma2d_tile<DT, SHAPE, r, T, V, NW, SP>(a, item - tile_start[j]);
+        if constexpr (use_rows<DT, SHAPE, r, T, SP>())
+            mfma2d_rows_tile<DT, SHAPE, r, T, V, NW>(a, item - tile_start[j]);
+        else
+            mfma2d_tile<DT, SHAPE, r, T, V, NW, SP>(a, item - tile_start[j]);
         __syncthreads();
     }
 }

@@ -117,6 +117,37 @@ void mfma_build_fragments(int shape, int d, int r, const double *w, int steps, i
     }
 }
 
+void mfma_build_row_fragments(int shape, int r, const double *w, int steps, int dtype,
+                              std::vector<uint8_t> *out)
+{
+    // Per non-empty k-block of each composite row a (rows -R .. R): 64 lanes
+    // x 8 weights; lane l holds A_a[i = l % 16][k = 32 kk + 8 (l / 16) + e].
+    out->clear();
+    const int R = r * steps;
+    const int side = 2 * R + 1;
+    const int dl = rows_delta(R);
+    std::vector<double> wc;
+    compose_dense(shape, 2, r, w, steps, &wc);
+    out->assign((size_t)rows_total_frags(shape, r, steps) * 64 * 8 * 2, 0);
+    size_t frag = 0;
+    for (int a = -R; a <= R; ++a) {
+        const int nb = rows_nblk(shape, r, steps, a);
+        const int klo = rows_kk_lo(shape, r, steps, a);
+        for (int ib = 0; ib < nb; ++ib, ++frag) {
+            for (int l = 0; l < 64; ++l) {
+                const int i = l % 16, q = l / 16;
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 32 * (klo + ib) + 8 * q + e;
+                    const int b = k - R - dl - i;  // column offset of the weight
+                    const double v = (b >= -R && b <= R) ? wc[(size_t)(a + R) * side + (b + R)] : 0.0;
+                    const uint16_t bits = dtype == STENCIL_F16 ? f16_bits(v) : bf16_bits(v);
+                    std::memcpy(out->data() + ((frag * 64 + l) * 8 + e) * 2, &bits, 2);
+                }
+            }
+        }
+    }
+}
+
 void mfma_build_sparse_fragments(int shape, int r, const double *w, int steps, int dtype,
                                  std::vector<uint8_t> *out)
 {

@@ -72,6 +72,42 @@ __host__ __device__ constexpr int band_total_frags(int shape, int r, int t, int 
     return off;
 }
 
+// Row layout of the 16-bit matrix path (d = 2): the composite is applied as a
+// sum over its rows a of products D' = A_a B_a in which the 16 x 16 output
+// tile appears transposed (D'[i][j] = out[row m0 + j][col c + i]):
+//   A_a[i][k] = w_t[a][k - R - delta - i]   (band of the composite's row a),
+//   B_a[k][j] = u[m0 + j + a][c - R - delta + k],
+// so operand B is 8 consecutive columns of one data row per lane (a 16-byte
+// read of a row-major block) and each lane's outputs are 4 consecutive
+// columns of one row.  delta = (-R) mod 8 aligns the data window to 8
+// columns.  Row a has non-zeros for |b| <= amax(a) (band_amax with the axes
+// exchanged), so its k-blocks run from (R + delta - amax) / 32 to
+// (R + delta + amax + 15) / 32.
+__host__ __device__ constexpr int rows_delta(int R) { return (8 - R % 8) % 8; }
+__host__ __device__ constexpr int rows_kk_lo(int shape, int r, int t, int a)
+{
+    return (r * t + rows_delta(r * t) - band_amax(shape, r, t, 0, a)) / 32;
+}
+__host__ __device__ constexpr int rows_kk_hi(int shape, int r, int t, int a)
+{
+    return (r * t + rows_delta(r * t) + band_amax(shape, r, t, 0, a) + 15) / 32;
+}
+__host__ __device__ constexpr int rows_nblk(int shape, int r, int t, int a)
+{
+    return band_amax(shape, r, t, 0, a) < 0 ? 0 : rows_kk_hi(shape, r, t, a) - rows_kk_lo(shape, r, t, a) + 1;
+}
+// Fragments stored before row a (rows ordered -R .. R).
+__host__ __device__ constexpr int rows_frag_offset(int shape, int r, int t, int a)
+{
+    int off = 0;
+    for (int aa = -r * t; aa < a; ++aa) off += rows_nblk(shape, r, t, aa);
+    return off;
+}
+__host__ __device__ constexpr int rows_total_frags(int shape, int r, int t)
+{
+    return rows_frag_offset(shape, r, t, r * t + 1);
+}
+
 // 2:4 structured-sparse layout (d = 2, 16-bit operands, composite radius
 // R <= 7).  One v_smfmac_f32_16x16x64 covers two non-empty kernel columns
 // (b, b') of a 16-row output tile: its 64 dense k positions are 16 groups of

@@ -80,7 +80,9 @@ MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype)
     const double KT = (double)fused_points(shape, d, r, steps);
     // MACs issued per output point: KDIM per structurally non-zero k-block of
     // every column band (see mfma_layout.h)
-    const double executed = (double)band_total_frags(shape, r, steps, L.kdim, d) * L.kdim;
+    double executed = (double)band_total_frags(shape, r, steps, L.kdim, d) * L.kdim;
+    if (mfma_row_layout(dtype, d, shape, r, steps))  // 16-bit row layout: per k-block of each row
+        executed = (double)rows_total_frags(shape, r, steps) * L.kdim;
     L.S = KT / executed;
     return L;
 }

@@ -250,6 +250,8 @@ void build_fragments(const stencil_plan_s *p, int t, std::vector<uint8_t> *hi, s
         mfma_build_sparse_fragments(p->shape, p->r, p->w.data(), t, p->dtype, hi);
     else if (p->path == STENCIL_PATH_MFMA_SEQ)  // the single step's band, whatever the depth
         mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), 1, p->dtype, hi, lo);
+    else if (mfma_row_layout(p->dtype, p->d, p->shape, p->r, t))
+        mfma_build_row_fragments(p->shape, p->r, p->w.data(), t, p->dtype, hi);
     else
         mfma_build_fragments(p->shape, p->d, p->r, p->w.data(), t, p->dtype, hi, lo);
 }
