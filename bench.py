@@ -223,6 +223,36 @@ def section_c3(stl, args):
     return res
 
 
+def measured_ceilings(stl):
+    """Microbenchmarked ceilings per dtype (the model's second column): HBM
+    copy bandwidth, FMA chains on the vector units (float32 with vector
+    operands, as the kernels use), dense matrix-core rates; the sparse
+    matrix rate is taken as twice the dense one (not measured)."""
+    m = {k: stl.microbench(k) for k in ("copy", "fma_f64", "fma_f32_vgpr", "mfma_f64", "mfma_f32", "mfma_bf16")}
+    hw = {}
+    for dt, valu, mfma in (("f64", "fma_f64", "mfma_f64"), ("f32", "fma_f32_vgpr", "mfma_f32"),
+                           ("bf16", "fma_f32_vgpr", "mfma_bf16"), ("f16", "fma_f32_vgpr", "mfma_bf16"),
+                           ("bf16x3", "fma_f32_vgpr", "mfma_bf16")):
+        hw[dt] = dict(BB=m["copy"], PP_valu=m[valu], PP_mfma=m[mfma], PP_mfma_sparse=2 * m[mfma])
+    log("measured ceilings: " + ", ".join(f"{k} {v / 1e12:.2f}" for k, v in m.items()))
+    return dict(raw=m, per_dtype=hw)
+
+
+def parse_case(name):
+    """(shape, d, r, dtype, T) of a variant name such as box-2d3r-f64-T2."""
+    m = re.match(r"(box|star)-(\d)d(\d)r-(\w+)-T(\d+)", name)
+    return (m.group(1), int(m.group(2)), int(m.group(3)), m.group(4), int(m.group(5))) if m else None
+
+
+def predicted_with(stl, hw, name):
+    c = parse_case(name)
+    if not c or not hw:
+        return None
+    shape, d, r, dt, T = c
+    m = stl.model_predict(shape, d, r, T, dt, hw=hw["per_dtype"][dt])
+    return {-1: "valu", 0: "tie", 1: "mfma"}[m["winner"]]
+
+
 def model_check(c2, c3):
     rows = []
     pairs = {}
@@ -766,6 +796,8 @@ def summaries(variants, mcheck, precision, serving, cases, sparse=None, grid=Non
         out["variants_gst"] = {k.replace("-2d3r", ""): _r(r["gst"]) for k, r in variants.items()}
     if mcheck:
         out["model_check"] = f"{mcheck['agree']}/{mcheck['total']}"
+        if "agree_measured_ceilings" in mcheck:
+            out["model_check_measured_ceilings"] = f"{mcheck['agree_measured_ceilings']}/{mcheck['total']}"
     if precision:
         out["precision"] = {k: [_r(v["gst"]), _sig(v.get("oracle_e2e_1000", v["err_every_100"][-1])),
                                 _sig(v.get("oracle_arith_1000"))]
@@ -782,6 +814,8 @@ def summaries(variants, mcheck, precision, serving, cases, sparse=None, grid=Non
                                   c["predicted"], c.get("measured")] for k, c in cases.items()}
     if grid:
         out["grid_model_check"] = f"{grid['agree']}/{grid['total']}"
+        if "agree_measured_ceilings" in grid:
+            out["grid_model_check_measured_ceilings"] = f"{grid['agree_measured_ceilings']}/{grid['total']}"
     if seq:
         out["sequential"] = {k.replace("-2d", "").replace("-8192", "").replace("-16384", ""):
                              [_r(c["mfma"]) if isinstance(c["mfma"], float) else None,
@@ -873,9 +907,30 @@ def main():
     if roof:
         roof["traffic"] = recorded_traffic(head_name)
     mcheck = model_check(c2, c3) if (c2 or c3) else None
+    ceil = None
+    if mcheck or grid:
+        try:
+            ceil = measured_ceilings(stl)
+        except Exception as e:  # the datasheet column stands alone then
+            log(f"measured ceilings unavailable: {e}")
+    if ceil:
+        for rows in ([mcheck["cases"]] if mcheck else []) + ([list(grid["cases"].items())] if grid else []):
+            for item in rows:
+                name, row = (item["case"], item) if isinstance(item, dict) else item
+                if "measured" not in row:
+                    continue
+                row["predicted_measured_ceilings"] = predicted_with(stl, ceil, name)
+        if mcheck:
+            mcheck["agree_measured_ceilings"] = sum(r.get("predicted_measured_ceilings") == r["measured"]
+                                                    for r in mcheck["cases"])
+        if grid:
+            rows = [r for r in grid["cases"].values() if "measured" in r]
+            grid["agree_measured_ceilings"] = sum(r.get("predicted_measured_ceilings") == r["measured"]
+                                                  for r in rows)
     detail = {
         "headline": head_name, "roofline": roof or None, "cpu_baseline": cpu, "clocks": clocks,
-        "variants": ok, "model_check": mcheck, "precision": c4, "serving": c5, "paper_cases": cases,
+        "variants": ok, "model_check": mcheck, "ceilings": ceil, "precision": c4, "serving": c5,
+        "paper_cases": cases,
         "sparse": sparse, "grid": grid, "sequential": seq,
         "summary_keys": SUMMARY_KEYS,
     }

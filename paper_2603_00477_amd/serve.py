@@ -93,10 +93,15 @@ class GpuExecutor:
     Jobs are spread over `streams` HIP streams (default priority) by kernel
     variant: all jobs of one variant share a stream, so their passes of a
     round go out as one batched launch, while other variants' launches can
-    overlap with them on the device.  A job stays on its stream, so its passes
-    run in order."""
+    overlap with them on the device; grids of 2^24 points or more take the
+    streams in turn, so that a large pass does not hold back the small jobs
+    of its variant (measured on the 4096-job stream at 0.8 load: p99 112 ms
+    against 162 ms with every job on its variant's stream and 135 ms with 2D
+    jobs on one stream and 3D jobs in turn).  A job stays on its stream, so
+    its passes run in order."""
 
-    def __init__(self, device="cuda", stream=None, streams=4, autotune=True, tune_candidates=3):
+    def __init__(self, device="cuda", stream=None, streams=4, autotune=True, tune_candidates=3,
+                 stream_policy="size"):
         import torch
 
         import paper_2603_00477_amd as stl
@@ -108,6 +113,8 @@ class GpuExecutor:
         self.streams = [first] + [torch.cuda.Stream(device=self.device) for _ in range(max(0, streams - 1))]
         self.stream = first
         self.autotune = bool(autotune)
+        self.stream_policy = stream_policy
+        self._rr = 0
         self.tune_candidates = int(tune_candidates)
         self.choices = {}  # problem class -> (path, T, rows, GStencil/s measured when tuned)
 
@@ -125,9 +132,26 @@ class GpuExecutor:
         return int(np.prod(job.dims)) * D
 
     def _stream_index(self, info) -> int:
-        """Stream of a kernel variant (all jobs of a variant on one stream)."""
+        """Stream of a job.  "variant": all jobs of a kernel variant share a
+        stream (their passes batch); "dim": 2D jobs on stream 0 (batched),
+        3D jobs round-robin over the others (overlapping launches);
+        "size": like "variant" for grids under 2^24 points, large grids
+        round-robin over the streams (a large pass does not hold back the
+        small jobs batched with it)."""
+        n = len(self.streams)
+        if n == 1:
+            return 0
         key = (info["shape"], info["d"], info["r"], info["T"], info["dtype"], info["path"])
-        return hash(key) % len(self.streams)
+        npts = int(np.prod(info["dims"]))
+        if self.stream_policy == "dim":
+            if info["d"] == 2:
+                return 0
+            self._rr += 1
+            return 1 + self._rr % (n - 1)
+        if self.stream_policy == "size" and npts >= (1 << 24):
+            self._rr += 1
+            return self._rr % n
+        return hash(key) % n
 
     def prepare(self, job):
         torch = self.torch
