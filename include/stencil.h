@@ -270,9 +270,10 @@ typedef struct {
     int winner;          /* -1 VALU, 0 tie (ratio in [0.87, 1.15]), +1 MFMA    */
     /* Halo terms of this library's tilings (the paper's model omits halos and
      * attributes measured excess work to their recomputation):              */
-    double halo_valu;    /* executed / useful VALU FMAs: the skirt of r*T points
-                            each fused tile recomputes (1 for one-step passes
-                            whose halo is staged)                             */
+    double halo_valu;    /* executed / useful VALU FMAs in the tile plane: the
+                            ring each fused tile recomputes (r*T points per
+                            side in 2D; r*(T-1) in 3D, whose input halo is
+                            staged; 1 for one-step 3D passes)                 */
     double C_mfma_seq;   /* executed flops per point per pass of sequential-step
                             MFMA fusion (alpha = 1): T single-step band
                             products over step regions widened by the halo and

@@ -106,7 +106,7 @@ def _stencil_kernels(by):
     """Stencil kernel names in order of first dispatch, with averaged counters."""
     out = []
     for name, disp in by.items():
-        if "stl::" not in name or ("valu" not in name and "mfma" not in name):
+        if "stl::" not in name or not any(k in name for k in ("valu", "mfma", "fused3d")):
             continue
         first = min(disp)
         avg = {}

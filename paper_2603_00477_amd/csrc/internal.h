@@ -108,6 +108,7 @@ const std::vector<KernelEntry> &valu2d_table_bf16();
 const std::vector<KernelEntry> &valu2d_table_f16();
 const std::vector<KernelEntry> &valu2d_table_x3();  // float storage, FP64 arithmetic
 const std::vector<KernelEntry> &valu3d_kernels();
+const std::vector<KernelEntry> &valu3d_fused_kernels();
 const std::vector<KernelEntry> &valu3d_box_kernels();  // boxes r >= 2, one step per pass
 const std::vector<KernelEntry> &valu2d_table_cases();  // r = 7, and r = 1 with T = 5..8
 const std::vector<KernelEntry> &mfma2d_table_cases();  // composite radius 7

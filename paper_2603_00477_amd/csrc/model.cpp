@@ -93,7 +93,7 @@ MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype)
 // (TY WY) x (TX W) points keeps (TY WY - 2 EY) x (TX W - 2 EX), EY = r T for
 // fused passes (one-step passes stage their halo: no skirt); the thread tiles
 // are those the 3D launcher picks.
-static double valu_halo_factor(int d, int r, int T, int dtype)
+static double valu_halo_factor(int shape, int d, int r, int T, int dtype)
 {
     const int D = dtype_bytes(dtype);
     const int W = 16 / D > 8 ? 8 : 16 / D;
@@ -102,12 +102,15 @@ static double valu_halo_factor(int d, int r, int T, int dtype)
         return (64.0 * W) / (64.0 * W - 2.0 * E);
     }
     if (T == 1) return 1.0;
-    const int WY = r * T >= 6 ? (r >= 3 ? 2 : 1) : 2;
-    const int TX = 16, TY = r * T >= 6 ? 32 / WY : 16;
-    const int EY = r * T, EX = (EY + W - 1) / W * W;
-    const double PY = TY * WY, PX = TX * W;
-    if (PY <= 2 * EY || PX <= 2 * EX) return 0.0;
-    return PY * PX / ((PY - 2.0 * EY) * (PX - 2.0 * EX));
+    // fused 3D passes: every step computes the L1 x M1 layout (2 rows x W
+    // columns per thread, 16 x 32 threads for stars, 16 x 16 for boxes); the
+    // input halo is staged, so the output tile is the layout less r (T - 1)
+    // per side, the left margin rounded up to a whole vector
+    const int L1 = 2 * (shape == STENCIL_STAR ? 32 : 16), M1 = 16 * W;
+    const int SK = r * (T - 1), SKL = (SK + W - 1) / W * W;
+    const int BY = L1 - 2 * SK, BX = (M1 - SKL - SK) / W * W;
+    if (BY <= 0 || BX <= 0) return 0.0;
+    return (double)L1 * M1 / ((double)BY * BX);
 }
 
 // Executed flops per point per pass of sequential-step MFMA fusion: each of
@@ -223,7 +226,7 @@ extern "C" int stencil_model_predict(const stencil_model_in_t *in, const stencil
     o.scenario = !cu_cb ? (!tc_cb ? 1 : 2) : (!tc_cb ? 3 : 4);
     o.sweet_spot = o.gamma * o.alpha < o.S * PPm / H.PP_valu;
     o.winner = o.ratio < 0.87 ? -1 : (o.ratio > 1.15 ? 1 : 0);
-    o.halo_valu = valu_halo_factor(in->d, in->r, T, in->dtype);
+    o.halo_valu = valu_halo_factor(in->shape, in->d, in->r, T, in->dtype);
     if (in->d == 2 && in->dtype != STENCIL_F32_BF16X3) {
         o.C_mfma_seq = mfma_seq_flops(in->shape, in->r, T, in->dtype);
         const double useful = o.C_valu;  // 2 K T per point per pass

@@ -115,7 +115,7 @@ hipError_t stage_job_table(BatchStaging *stage, const void *jobs, size_t job_byt
 std::vector<const std::vector<KernelEntry> *> all_kernel_tables()
 {
     return {&valu2d_table_f64(),   &valu2d_table_f32(),  &valu2d_table_bf16(), &valu2d_table_f16(),
-            &valu2d_table_x3(),    &valu3d_kernels(),    &valu3d_box_kernels(), &valu2d_table_cases(),
+            &valu2d_table_x3(),    &valu3d_fused_kernels(), &valu3d_kernels(),    &valu3d_box_kernels(), &valu2d_table_cases(),
             &mfma2d_table_cases(), &mfma3d_table_cases(), &mfma2d_table_f64(),  &mfma2d_table_f32(),
             &mfma2d_table_bf16(),  &mfma2d_table_f16(),  &mfma2d_table_x3(),    &mfma3d_table_f64(),
             &mfma3d_table_f32(),   &mfma2d_table_sparse(), &mfma2d_table_seq(),

@@ -1,18 +1,17 @@
-// VALU path, d = 3: T explicit steps fused per pass, streaming along z (the
-// slowest axis).
+// VALU path, d = 3, one explicit step per pass, streaming along z (the
+// slowest axis).  Passes of T >= 2 fused steps run on the kernel of
+// valu3d_fused.hip; the step pipeline below is written for any T, but the
+// tile geometry (no skirt, halo staged per thread) is the one-step one.
 //
-// A workgroup of TX x TY threads owns an extended in-plane tile of
-// (TY*WY) x (TX*W) points (each thread WY rows x W consecutive columns) and
-// streams down a segment of planes.  A fused pass's tile carries a skirt of
-// R*T points on every side for the later steps; the valid output tile is the
-// interior.  A one-step pass stages the plane's R-point halo around the tile
-// as well and has no skirt.
-// The step pipeline is the one of the 2D kernel with rows replaced by planes:
-// stage 0 writes input plane k to an LDS plane buffer; stage s reads the plane
-// stage s-1 wrote one iteration earlier, scatters it into 2R+1 rotating
-// accumulator planes (input plane z adds its in-plane neighbourhood weighted
-// by w[c][.][.] to output plane z-c) and emits the completed plane.  One
-// barrier per plane.
+// A workgroup of TX x TY threads owns an in-plane tile of (TY*WY) x (TX*W)
+// points (each thread WY rows x W consecutive columns) and streams down a
+// segment of planes.  Each thread stages its own points of a plane and a
+// share of the plane's R-point halo around the tile (prefetched U planes
+// ahead), so every computed point is an output.
+// Stage 0 writes input plane k to an LDS plane buffer; stage 1 reads the plane
+// written one iteration earlier, scatters it into 2R+1 rotating accumulator
+// planes (input plane z adds its in-plane neighbourhood weighted by w[c][.][.]
+// to output plane z-c) and emits the completed plane.  One barrier per plane.
 //
 // Weights: a set of up to 48 dwords lives in scalar registers, up to 64
 // dwords is pinned in vector registers.  Boxes with r >= 2 (125 or 343
@@ -46,15 +45,12 @@ struct Valu3DCfg {
     static constexpr int NT = TX * TY;
     static constexpr int PY = TY * WY;                      // extended rows
     static constexpr int PX = TX * W;                       // extended columns
-    // One-step passes (HALO) stage the input plane's R-point halo around the
-    // tile as well (prefetched U planes ahead with the tile), so the tile
-    // needs no skirt: every computed point is an output (+25-31 % measured at
-    // 512^3).  Fused passes stage the tile only and carry a skirt of R T
-    // points (staging the halo there, for a skirt of R (T - 1), measured up
-    // to 7 % slower at T = 2 and up to 25 % at T = 3).
-    static constexpr bool HALO = T == 1;
-    static constexpr int EY = HALO ? 0 : R * T;           // row skirt
-    static constexpr int EX = ((EY + W - 1) / W) * W;     // column skirt (vector aligned)
+    // The tile stages the input plane's R-point halo (no skirt): staging a
+    // halo instead of computing a skirt measured +25-31 % at 512^3.
+    static_assert(T == 1, "fused passes run on the fused 3D kernel");
+    static constexpr bool HALO = true;
+    static constexpr int EY = 0;                            // row skirt
+    static constexpr int EX = 0;                            // column skirt
     static constexpr int PADX = ((R + W - 1) / W) * W;      // LDS column pad
     static constexpr int LDX = PX + 2 * PADX;               // LDS row pitch
     static constexpr int LROWS = PY + 2 * R;                // LDS rows (R pad each side)
@@ -499,20 +495,16 @@ hipError_t launch_valu3d_batch_cfg(const PassArgs *ps, int n, BatchStaging *stag
     return hipGetLastError();
 }
 
-// Tile shapes: 16 x 16 threads (32 x 8 for one step per pass); float64 2 x 2
-// points per thread, float32 2 x 4, 16-bit storage 2 x 8.
-//   one step per pass, r <= 2: 32 x 8 threads (wide rows: 64 float64 / 128
-//   float32 columns per tile), measured 14-18 % faster than 16 x 16 on 512^3;
-//   r = 3 (Star-3D3R float32: 371 vs 294 GSt/s) and fused passes keep 16 x 16;
-//   deep composite halos (r T >= 6): 4 rows per thread spilled to AGPRs;
-//   measured on 512^3, Star-3D2R T = 3 runs best with 1 row x 32 thread rows
-//   (+26-36 %), Star-3D3R T = 2 with 2 rows x 16 (+25 %).
+// Tile shapes: float64 2 x 2 points per thread, float32 2 x 4.  r <= 2:
+// 32 x 8 threads (wide rows: 64 float64 / 128 float32 columns per tile),
+// measured 14-18 % faster than 16 x 16 on 512^3; r = 3 keeps 16 x 16
+// (Star-3D3R float32: 371 vs 294 GSt/s).
 template <typename TS, int R, int T>
 struct Valu3DShape {
     static constexpr int W = sizeof(TS) == 8 ? 2 : (sizeof(TS) == 4 ? 4 : 8);
-    static constexpr int WY = (T == 1 && R <= 2) ? 2 : (R * T >= 6 ? (R >= 3 ? 2 : 1) : 2);
-    static constexpr int TX = (T == 1 && R <= 2) ? 32 : 16;
-    static constexpr int TY = (T == 1 && R <= 2) ? 8 : (R * T >= 6 ? 32 / WY : 16);
+    static constexpr int WY = 2;
+    static constexpr int TX = R <= 2 ? 32 : 16;
+    static constexpr int TY = R <= 2 ? 8 : 16;
 };
 
 template <typename TS, typename TC, int SHAPE, int R, int T>
@@ -531,13 +523,11 @@ hipError_t launch_valu3d_batch(const PassArgs *ps, int n, BatchStaging *stage, h
 
 #define V3(TS, TC, DT, SH, R, T) \
     {STENCIL_PATH_VALU, DT, SH, 3, R, T, &launch_valu3d<TS, TC, SH, R, T>, &launch_valu3d_batch<TS, TC, SH, R, T>}
-#define V3_T(TS, TC, DT, SH, R) V3(TS, TC, DT, SH, R, 1), V3(TS, TC, DT, SH, R, 2), V3(TS, TC, DT, SH, R, 3)
-// Instantiated (shape, r, T): those that fit the register file without
-// spilling; other combinations run as single-step passes of the direct kernel.
-#define V3_S(TS, TC, DT)                                                                      \
-    V3_T(TS, TC, DT, STENCIL_STAR, 1), V3_T(TS, TC, DT, STENCIL_STAR, 2),                     \
-        V3(TS, TC, DT, STENCIL_STAR, 3, 1), V3(TS, TC, DT, STENCIL_STAR, 3, 2),               \
-        V3_T(TS, TC, DT, STENCIL_BOX, 1)
+// One-step passes (T = 1) of every star radius up to 3 and of the 27-point
+// box; fused passes (T >= 2) run on the kernel of valu3d_fused.hip.
+#define V3_S(TS, TC, DT)                                                                       \
+    V3(TS, TC, DT, STENCIL_STAR, 1, 1), V3(TS, TC, DT, STENCIL_STAR, 2, 1), V3(TS, TC, DT, STENCIL_STAR, 3, 1), \
+        V3(TS, TC, DT, STENCIL_BOX, 1, 1)
 
 }  // namespace
 

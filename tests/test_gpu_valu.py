@@ -150,6 +150,27 @@ def test_valu3d(stl, shape, r, T, dt, boundary):
     assert rel_inf(got, ref) <= TOL[dt]
 
 
+FUSED3 = [("star", 1, 2), ("star", 1, 3), ("star", 2, 2), ("star", 2, 3), ("star", 3, 2), ("box", 1, 2),
+          ("box", 1, 3)]
+
+
+@pytest.mark.parametrize("shape,r,T", FUSED3)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
+@pytest.mark.parametrize("dims", [(21, 150, 144), (17, 131, 141)])
+def test_valu3d_fused_many_tiles(stl, shape, r, T, dt, boundary, dims):
+    """Fused 3D passes (T >= 2) over several in-plane tiles of the largest
+    thread layouts, with ragged edges, rows whose length is and is not a
+    whole number of vectors, and a remainder pass (2T + 1 steps)."""
+    u0, u0r, t, w = case_inputs(shape, 3, r, dims, dt, seed=5700 + 10 * r + T + dims[2])
+    steps = 2 * T + 1
+    p = stl.Plan(shape, 3, r, w, dims, T=T, dtype=dt, path="valu", boundary=boundary, halo=0.5)
+    assert p.info()["T_fused"] == T
+    got = run_gpu(p, t, steps)
+    ref = oracle(shape, 3, r, w, u0, steps, boundary, 0.5)
+    assert rel_inf(got, ref) <= TOL[dt]
+
+
 @pytest.mark.parametrize("dims", [(1, 1, 1), (3, 5, 7), (2, 9, 70), (9, 17, 3)])
 @pytest.mark.parametrize("shape,r", [("star", 2), ("box", 1), ("star", 3)])
 @pytest.mark.parametrize("boundary", ["dirichlet", "periodic"])
