@@ -96,7 +96,9 @@ MfmaLayout mfma_layout(int shape, int d, int r, int steps, int dtype)
 static double valu_halo_factor(int shape, int d, int r, int T, int dtype)
 {
     const int D = dtype_bytes(dtype);
-    const int W = 16 / D > 8 ? 8 : 16 / D;
+    const int W16 = 16 / D > 8 ? 8 : 16 / D;
+    // columns per lane of the 2D kernel: one 16-byte vector, two for float64 at T = 2
+    const int W = (d == 2 && D == 8 && T == 2) ? 2 * W16 : W16;
     if (d == 2) {
         const int E = (r * T + W - 1) / W * W;
         return (64.0 * W) / (64.0 * W - 2.0 * E);

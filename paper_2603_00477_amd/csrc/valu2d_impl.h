@@ -73,19 +73,24 @@ struct Valu2DCfg {
     // input rows in flight: U for small Q; for r = 7 (Q = 15, compute-bound,
     // 225 or 29 FMAs per input value) 3 rows, a divisor of U, so the ring
     // slot of row k is k mod P at compile time and 48 VGPRs stay free
-    static constexpr int P = U <= 8 ? U : (U % 3 == 0 ? 3 : (U % 4 == 0 ? 4 : (U % 5 == 0 ? 5 : U)));
+    // 32-byte lanes (float64 at T = 2) prefetch one row: their rows take
+    // twice the arithmetic, and the registers go to the wider accumulators
+    static constexpr int P = sizeof(TS) * W > 16 ? 1
+                             : (U <= 8 ? U : (U % 3 == 0 ? 3 : (U % 4 == 0 ? 4 : (U % 5 == 0 ? 5 : U))));
     // Boxes whose weights exceed 48 dwords (float64 r >= 2, float32 r = 3)
     // fused over T >= 3 steps keep them out of the vector registers: stored
     // column-major (w[b][a]), each column of 2R+1 is scalar-loaded just before
     // its FMAs.  That frees 49-98 VGPRs for the T stages' accumulators
     // (Box-2D3R float64 T = 4: 232 instead of 340 registers, no spills, +30 %
     // measured).  Float64 at T = 1 streams them too (Box-2D3R: 88 instead of
-    // 236 VGPRs; +9 % measured at 10240^2, equal at 8192^2).  At T = 2 the
-    // weights pinned in VGPRs measured faster (float32: 632 vs 478 GSt/s;
-    // float64: 340 vs 329), so they stay there unless they need more than 128
-    // dwords (r = 7: 225 weights).
+    // 236 VGPRs; +9 % measured at 10240^2, equal at 8192^2).  Float32 at T = 2
+    // keeps them pinned in VGPRs (632 vs 478 GSt/s measured) unless they need
+    // more than 128 dwords (r = 7: 225 weights).  Float64 at T = 2 runs
+    // 32-byte lanes, which stream them too: each weight then serves four
+    // columns, and the freed registers hold the wider accumulators at two
+    // waves per SIMD.
     static constexpr bool WPTR = SHAPE == STENCIL_BOX && sizeof(TC) * K > 192 &&
-                                 (T >= 3 || (sizeof(TC) == 8 && T == 1) || sizeof(TC) * K > 512);
+                                 (T >= 3 || sizeof(TC) == 8 || sizeof(TC) * K > 512);
 };
 
 // Weights in constant memory (scalar loads).
@@ -145,7 +150,14 @@ __device__ __forceinline__ void assemble_window(const TC (&own)[W], TC (&win)[W 
 }
 
 // One tile (column band x row segment) of one pass, run by one wave.
-template <typename TS, typename TC, int SHAPE, int R, int T, int W>
+// FAST: the grid rows are whole aligned vectors and the output box starts on
+// a vector boundary, so every lane's W columns lie wholly inside or wholly
+// outside the grid.  Row loads are then one unconditional vector load per
+// row (periodic lanes and rows wrap by whole vectors; Dirichlet ones outside
+// the grid load a valid dummy and take h when the row is consumed); with no
+// other write to the prefetch ring, the compiler waits only for the row being
+// consumed and the loads of the next rows stay in flight.
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, bool FAST>
 __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                                             const TC (&wk)[Valu2DCfg<TS, TC, SHAPE, R, T, W>::WPTR
                                                                ? 1
@@ -201,8 +213,26 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
 #pragma unroll
         for (int j = 0; j < W + 2 * R; ++j) wins[s][j] = TC(0);
 
+    // fast path: the lane's source column (wrapped, or a valid dummy) and
+    // whether its vector lies outside a Dirichlet grid
+    int f_col = cb;
+    bool f_h = false;
+    if constexpr (FAST) {
+        if (periodic) {
+            f_col = wrap(cb, n1);
+        } else {
+            const bool in = cb >= 0 && cb + W <= n1;
+            f_h = !in;
+            f_col = in ? cb : 0;
+        }
+    }
     auto load_row = [&](int k, Vec &v) {
         const int i = ybase + k;
+        if constexpr (FAST) {
+            const int ri = periodic ? wrap(i, n0) : min(max(i, 0), n0 - 1);
+            v.load(src + (int64_t)ri * n1 + f_col);
+            return;
+        }
         const bool row_in = i >= 0 && i < n0;
         if (!periodic && !row_in) {
 #pragma unroll
@@ -363,8 +393,17 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
             // ---- stage 0: input row (window for stage 1), prefetch P rows ahead
             {
                 TC inrow[W];
+                if constexpr (FAST) {
+                    const int i = ybase + k;
+                    const bool hrow = f_h || (!periodic && (i < 0 || i >= n0));
 #pragma unroll
-                for (int j = 0; j < W; ++j) inrow[j] = to_compute<TC>(ring[u % P].e[j]);
+                    for (int j = 0; j < W; ++j) inrow[j] = hrow ? h : to_compute<TC>(ring[u % P].e[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < W; ++j) inrow[j] = to_compute<TC>(ring[u % P].e[j]);
+                }
+                // keep the refill of this ring slot behind the reads that drain it
+                __builtin_amdgcn_sched_barrier(0);
                 if (k + P < KTOT) load_row(k + P, ring[u % P]);
                 assemble_window<TC, W, R>(inrow, wins[0], lane);
             }
@@ -388,6 +427,13 @@ __device__ __forceinline__ void load_weights(TC (&wk)[K], const SrcT *w)
         wk[k] = w[k];
         if constexpr (sizeof(TC) == 4 || (sizeof(TC) * K > 192 && !SCALAR64)) asm volatile("" : "+v"(wk[k]));
     }
+}
+
+// Whether a job's tiles take the fast row loads (see valu2d_tile).
+template <typename TS, int W, typename TC>
+__device__ __forceinline__ bool valu2d_fast(const Valu2DJob<TC> &g)
+{
+    return vec_aligned<TS, W>(g.src, g.n1, 0) && (g.ox0 % W) == 0;
 }
 
 template <typename TS, typename TC, int SHAPE, int R, int T, int W>
@@ -415,7 +461,10 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_kernel(
     } else {
         load_weights<TC, Cfg::K, SHAPE == STENCIL_STAR && R == 7>(wk, a.w);
     }
-    valu2d_tile<TS, TC, SHAPE, R, T, W>(a.g, wk, wp, band, g % a.g.nsegs, threadIdx.x & 63);
+    if (valu2d_fast<TS, W>(a.g))
+        valu2d_tile<TS, TC, SHAPE, R, T, W, true>(a.g, wk, wp, band, g % a.g.nsegs, threadIdx.x & 63);
+    else
+        valu2d_tile<TS, TC, SHAPE, R, T, W, false>(a.g, wk, wp, band, g % a.g.nsegs, threadIdx.x & 63);
 }
 
 // One job of a batched launch: geometry plus weights.
@@ -452,20 +501,27 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
         } else {
             load_weights<TC, Cfg::K, SHAPE == STENCIL_STAR && R == 7>(wk, jobs[j].w);
         }
-        valu2d_tile<TS, TC, SHAPE, R, T, W>(g, wk, wp, band, local % g.nsegs, lane);
+        if (valu2d_fast<TS, W>(g))
+            valu2d_tile<TS, TC, SHAPE, R, T, W, true>(g, wk, wp, band, local % g.nsegs, lane);
+        else
+            valu2d_tile<TS, TC, SHAPE, R, T, W, false>(g, wk, wp, band, local % g.nsegs, lane);
     }
 }
 
-template <typename TS>
+// Columns per lane: one 16-byte vector, except float64 at T = 2, which takes
+// two (256-column bands: the 2E-column skirt is half the share of the band;
+// Box-2D3R 8192^2: 368 vs 345 GSt/s, Star-2D3R: 580 vs 528).  At T = 1 and
+// T >= 3 the 2-column lanes measured faster (occupancy).
+template <typename TS, int T>
 struct Valu2DShape {
-    static constexpr int W = 16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS);
+    static constexpr int W = (sizeof(TS) == 8 && T == 2) ? 4 : (16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS));
 };
 
 // Fill the geometry of one pass; returns false when there is nothing to do.
 template <typename TS, typename TC, int SHAPE, int R, int T>
 bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
 {
-    using S = Valu2DShape<TS>;
+    using S = Valu2DShape<TS, T>;
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     *err = hipSuccess;
     g->src = p.src;
@@ -512,7 +568,7 @@ bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
 {
-    using S = Valu2DShape<TS>;
+    using S = Valu2DShape<TS, T>;
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     Valu2DArgs<TC, Cfg::K> a;
     hipError_t err;
@@ -537,7 +593,7 @@ hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
-    using S = Valu2DShape<TS>;
+    using S = Valu2DShape<TS, T>;
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     using Job = Valu2DBatchJob<TC, Cfg::K>;
     std::vector<Job> jobs;

@@ -51,14 +51,21 @@ template <typename TC> __device__ __forceinline__ TC to_compute(float v) { retur
 template <typename TC> __device__ __forceinline__ TC to_compute(__hip_bfloat16 v) { return (TC)__bfloat162float(v); }
 template <typename TC> __device__ __forceinline__ TC to_compute(__half v) { return (TC)__half2float(v); }
 
-// W consecutive storage elements moved with one 16-byte access when aligned.
+// W consecutive storage elements moved with 16-byte accesses when aligned
+// (one, or two for 32 bytes).
 template <typename TS, int W>
 struct RawVec {
     TS e[W];
     __device__ __forceinline__ void load(const TS *p)
     {
-        static_assert(sizeof(TS) * W == 16 || sizeof(TS) * W == 8 || sizeof(TS) * W == 4, "vector width");
-        if constexpr (sizeof(TS) * W == 16) {
+        static_assert(sizeof(TS) * W == 32 || sizeof(TS) * W == 16 || sizeof(TS) * W == 8 || sizeof(TS) * W == 4,
+                      "vector width");
+        if constexpr (sizeof(TS) * W == 32) {
+            const uint4 v0 = reinterpret_cast<const uint4 *>(p)[0];
+            const uint4 v1 = reinterpret_cast<const uint4 *>(p)[1];
+            __builtin_memcpy(e, &v0, 16);
+            __builtin_memcpy(reinterpret_cast<char *>(e) + 16, &v1, 16);
+        } else if constexpr (sizeof(TS) * W == 16) {
             const uint4 v = *reinterpret_cast<const uint4 *>(p);
             __builtin_memcpy(e, &v, 16);
         } else if constexpr (sizeof(TS) * W == 8) {
@@ -71,7 +78,13 @@ struct RawVec {
     }
     __device__ __forceinline__ void store(TS *p) const
     {
-        if constexpr (sizeof(TS) * W == 16) {
+        if constexpr (sizeof(TS) * W == 32) {
+            uint4 v0, v1;
+            __builtin_memcpy(&v0, e, 16);
+            __builtin_memcpy(&v1, reinterpret_cast<const char *>(e) + 16, 16);
+            reinterpret_cast<uint4 *>(p)[0] = v0;
+            reinterpret_cast<uint4 *>(p)[1] = v1;
+        } else if constexpr (sizeof(TS) * W == 16) {
             uint4 v;
             __builtin_memcpy(&v, e, 16);
             *reinterpret_cast<uint4 *>(p) = v;
