@@ -575,89 +575,80 @@ __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
     }
 }
 
-// 16-bit operands, row layout (mfma_layout.h): one 16V x 16NW output tile.
+// 16-bit operands, row layout (mfma_layout.h): 16V x 16NW output tiles.
 // The input block is staged row-major (16-byte loads and LDS writes, no
 // transposition); for every composite row a and k-block the wave issues one
 // MFMA per stacked tile with the weight band as operand A and 8 consecutive
 // columns of one data row per lane as operand B; the transposed 16 x 16
 // results give each lane 4 consecutive output columns of one row.
 template <int DT, int SHAPE, int r, int T, int V, int NW>
-__device__ __forceinline__ void mfma2d_rows_tile(const Mfma2DArgs &a, const int tile)
-{
+struct RowsCfg {
     using MT = MfmaTypes<DT>;
     using TS = typename MT::TS;
     using OP = typename MT::OP;
     using FR = typename MT::FR;
     using ACC = typename MT::ACC;
     static_assert(MT::KDIM == 32 && !MT::X3, "16-bit operands");
-    constexpr int R = r * T, DL = rows_delta(R);
-    constexpr int TR = 16 * V, TC = 16 * NW, NT = 64 * NW;
-    constexpr int LRD = TR + 2 * R;                                  // frame rows
-    constexpr int NKB0 = rows_nblk(SHAPE, r, T, 0) + rows_kk_lo(SHAPE, r, T, 0);  // widest row's k extent
-    constexpr int KMAX = 16 * (NW - 1) + 32 * NKB0;                  // frame columns read
-    constexpr int LCD = TC + 2 * R + DL;                             // frame columns holding data
-    constexpr int LCF = ((KMAX > LCD ? KMAX : LCD) + 7) / 8 * 8;     // staged columns
-    constexpr int PIT = (LCF / 8) % 2 ? LCF : LCF + 8;               // odd number of 16-byte units per row
-    constexpr int NFRAG = rows_total_frags(SHAPE, r, T);
-    constexpr bool ALDS = NFRAG <= 24;
+    static constexpr int R = r * T, DL = rows_delta(R);
+    static constexpr int TR = 16 * V, TC = 16 * NW, NT = 64 * NW;
+    static constexpr int LRD = TR + 2 * R;                                  // frame rows
+    static constexpr int NKB0 = rows_nblk(SHAPE, r, T, 0) + rows_kk_lo(SHAPE, r, T, 0);  // widest row's k extent
+    static constexpr int KMAX = 16 * (NW - 1) + 32 * NKB0;                  // frame columns read
+    static constexpr int LCD = TC + 2 * R + DL;                             // frame columns holding data
+    static constexpr int LCF = ((KMAX > LCD ? KMAX : LCD) + 7) / 8 * 8;     // staged columns
+    static constexpr int PIT = (LCF / 8) % 2 ? LCF : LCF + 8;               // odd number of 16-byte units per row
+    static constexpr int NFRAG = rows_total_frags(SHAPE, r, T);
+    static constexpr bool ALDS = NFRAG <= 24;
+    static constexpr int NCH = LCF / 8;                                     // 16-byte chunks per frame row
+    static constexpr int NE = (LRD * NCH + NT - 1) / NT;                    // chunks per thread
+    // a 16-byte chunk as a plain vector type (a struct with unions would be
+    // kept in scratch memory when it lives across a loop iteration)
+    typedef unsigned int Chunk __attribute__((ext_vector_type(4)));
 
-    __shared__ __attribute__((aligned(16))) OP lb[LRD * PIT];
-    __shared__ __attribute__((aligned(16))) FR lA[ALDS ? NFRAG * 64 : 1];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lg = lane >> 4, ln = lane & 15;
-    const int r0 = (tile / a.ntc) * TR, c0 = (tile % a.ntc) * TC;
-    const int n0 = a.n0, n1 = a.n1;
-    const bool periodic = a.periodic != 0;
-    const TS *src = static_cast<const TS *>(a.src);
-    const FR *afr = static_cast<const FR *>(a.afrag);
-    const int fr0 = r0 - R, fc0 = c0 - R - DL;  // frame origin in the grid (fc0 = 0 mod 8)
-
-    // A table: loads in flight during the staging
-    constexpr int NAT = ALDS ? (NFRAG * 64 + NT - 1) / NT : 1;
-    FR ta[NAT];
-    if constexpr (ALDS) {
+    // frame origin in the grid (column a multiple of 8)
+    __device__ __forceinline__ static int fr0(const Mfma2DArgs &a, int tile) { return (tile / a.ntc) * TR - R; }
+    __device__ __forceinline__ static int fc0(const Mfma2DArgs &a, int tile) { return (tile % a.ntc) * TC - R - DL; }
+    // interior tile: the frame lies inside the grid, rows of whole 16-byte units
+    __device__ __forceinline__ static bool fast(const Mfma2DArgs &a, int tile)
+    {
+        const int f0 = fr0(a, tile), g0 = fc0(a, tile);
+        return f0 >= 0 && f0 + LRD <= a.n0 && g0 >= 0 && g0 + LCF <= a.n1 && (a.n1 % 8) == 0 &&
+               (reinterpret_cast<uintptr_t>(a.src) % 16) == 0;
+    }
+    // issue the frame loads of an interior tile, chunks i = 0..NE-1 of this
+    // thread; clamped indices: every lane loads (in bounds), so the loads
+    // stay in flight together
+    __device__ __forceinline__ static void issue(const Mfma2DArgs &a, int tile, Chunk (&v)[NE], int tid)
+    {
+        const TS *src = static_cast<const TS *>(a.src);
+        const int f0 = fr0(a, tile), g0 = fc0(a, tile), n1 = a.n1;
 #pragma unroll
-        for (int i = 0; i < NAT; ++i) {
+        for (int i = 0; i < NE; ++i) {
             const int e = tid + i * NT;
-            if (e < NFRAG * 64) ta[i] = afr[e];
+            const int ec = e < LRD * NCH ? e : LRD * NCH - 1;
+            const int rowc = ec / NCH, chc = ec - rowc * NCH;
+            v[i] = *reinterpret_cast<const Chunk *>(src + (int64_t)(f0 + rowc) * n1 + g0 + 8 * chc);
         }
     }
-    // ---- stage the frame: interior tiles in 16-byte chunks (8 elements)
-    constexpr int NCH = LCF / 8;
-    const bool fast = fr0 >= 0 && fr0 + LRD <= n0 && fc0 >= 0 && fc0 + LCF <= n1 && (n1 % 8) == 0 &&
-                      (reinterpret_cast<uintptr_t>(src) % 16) == 0;
-    if (fast) {
-        constexpr int NE = (LRD * NCH + NT - 1) / NT;
-        constexpr int CB = NE < 8 ? NE : 8;
+    __device__ __forceinline__ static void write(const Chunk (&v)[NE], OP *lb, int tid)
+    {
 #pragma unroll
-        for (int e0 = 0; e0 < NE; e0 += CB) {
-            uint4 v[CB];
-#pragma unroll
-            for (int i = 0; i < CB; ++i) {
-                const int e = tid + (e0 + i) * NT;
-                const int row = e / NCH, ch = e - row * NCH;
-                // clamped index: every lane loads (in bounds), so the loads
-                // of a batch stay in registers and in flight together
-                const int ec = e < LRD * NCH ? e : LRD * NCH - 1;
-                const int rowc = ec / NCH, chc = ec - rowc * NCH;
-                (void)row;
-                (void)ch;
-                v[i] = *reinterpret_cast<const uint4 *>(src + (int64_t)(fr0 + rowc) * n1 + fc0 + 8 * chc);
-            }
-#pragma unroll
-            for (int i = 0; i < CB; ++i) {
-                const int e = tid + (e0 + i) * NT;
-                const int row = e / NCH, ch = e - row * NCH;
-                if (e0 + i < NE && e < LRD * NCH) *reinterpret_cast<uint4 *>(&lb[row * PIT + 8 * ch]) = v[i];
-            }
+        for (int i = 0; i < NE; ++i) {
+            const int e = tid + i * NT;
+            const int row = e / NCH, ch = e - row * NCH;
+            if (e < LRD * NCH) *reinterpret_cast<Chunk *>(&lb[row * PIT + 8 * ch]) = v[i];
         }
-    } else {
-        // edge tiles: element by element with the boundary rule; columns past
-        // the data (read only against zero weights) get zeros
+    }
+    // edge tiles: element by element with the boundary rule; columns past
+    // the data (read only against zero weights) get zeros
+    __device__ __forceinline__ static void stage_slow(const Mfma2DArgs &a, int tile, OP *lb, int tid)
+    {
+        const TS *src = static_cast<const TS *>(a.src);
+        const int f0 = fr0(a, tile), g0 = fc0(a, tile), n0 = a.n0, n1 = a.n1;
+        const bool periodic = a.periodic != 0;
         for (int e = tid; e < LRD * LCF; e += NT) {
             const int row = e / LCF, col = e - row * LCF;
-            int gr = fr0 + row, gc = fc0 + col;
+            int gr = f0 + row, gc = g0 + col;
             OP v = OP(0);
             if (col < LCD) {
                 const bool in = gr >= 0 && gr < n0 && gc >= 0 && gc < n1;
@@ -671,7 +662,90 @@ __device__ __forceinline__ void mfma2d_rows_tile(const Mfma2DArgs &a, const int 
             lb[row * PIT + col] = v;
         }
     }
-    if constexpr (ALDS) {
+    // MFMAs over the staged frame and the store of the tile
+    __device__ __forceinline__ static void compute_store(const Mfma2DArgs &a, int tile, const OP *lb, const FR *lA, int tid)
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        const int lg = lane >> 4, ln = lane & 15;
+        const FR *afr = static_cast<const FR *>(a.afrag);
+        ACC acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = ACC{};
+        const int colw = 16 * wave + 8 * lg;
+#pragma unroll
+        for (int ar = -R; ar <= R; ++ar) {
+            if (band_amax(SHAPE, r, T, 0, ar) < 0) continue;
+            const int klo = rows_kk_lo(SHAPE, r, T, ar), nb = rows_nblk(SHAPE, r, T, ar);
+            const int off = rows_frag_offset(SHAPE, r, T, ar);
+#pragma unroll
+            for (int ib = 0; ib < nb; ++ib) {
+                const FR A = ALDS ? lA[(off + ib) * 64 + lane] : afr[(off + ib) * 64 + lane];
+                const int col = colw + 32 * (klo + ib);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const FR B = *reinterpret_cast<const FR *>(&lb[(16 * v + ln + ar + R) * PIT + col]);
+                    acc[v] = mfma16(A, B, acc[v]);
+                }
+            }
+        }
+        // lane (lg, ln) holds row r0 + 16 v + ln, columns 4 lg .. 4 lg + 3
+        TS *dst = static_cast<TS *>(a.dst);
+        const int n0 = a.n0, n1 = a.n1;
+        const int r0 = (tile / a.ntc) * TR, c0 = (tile % a.ntc) * TC;
+        const int gc = c0 + 16 * wave + 4 * lg;
+        const bool vec = gc + 4 <= n1 && (n1 % 4) == 0 && (reinterpret_cast<uintptr_t>(dst) % 8) == 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int gr = r0 + 16 * v + ln;
+            if (gr >= n0 || gc >= n1) continue;
+            TS *p = dst + (int64_t)gr * n1 + gc;
+            if (vec) {
+                RawVec<TS, 4> ov;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ov.e[e] = to_storage<TS>(acc[v][e]);
+                ov.store(p);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (gc + e < n1) p[e] = to_storage<TS>(acc[v][e]);
+            }
+        }
+    }
+};
+
+// One tile per workgroup (a persistent grid of occupancy x CUs workgroups, each
+// prefetching its next tile's frame under the current tile's MFMAs, measured
+// 2x slower on 16384^2: the dispatcher balances tiles over CUs better).
+template <int DT, int SHAPE, int r, int T, int V, int NW>
+__device__ __forceinline__ void mfma2d_rows_tile(const Mfma2DArgs &a, const int tile)
+{
+    using C = RowsCfg<DT, SHAPE, r, T, V, NW>;
+    using FR = typename C::FR;
+    using OP = typename C::OP;
+    constexpr int NFRAG = C::NFRAG, NT = C::NT;
+    __shared__ __attribute__((aligned(16))) OP lb[C::LRD * C::PIT];
+    __shared__ __attribute__((aligned(16))) FR lA[C::ALDS ? NFRAG * 64 : 1];
+    const int tid = threadIdx.x;
+    const FR *afr = static_cast<const FR *>(a.afrag);
+
+    // A table: loads in flight during the staging
+    constexpr int NAT = C::ALDS ? (NFRAG * 64 + NT - 1) / NT : 1;
+    FR ta[NAT];
+    if constexpr (C::ALDS) {
+#pragma unroll
+        for (int i = 0; i < NAT; ++i) {
+            const int e = tid + i * NT;
+            if (e < NFRAG * 64) ta[i] = afr[e];
+        }
+    }
+    if (C::fast(a, tile)) {
+        typename C::Chunk v[C::NE];
+        C::issue(a, tile, v, tid);
+        C::write(v, lb, tid);
+    } else {
+        C::stage_slow(a, tile, lb, tid);
+    }
+    if constexpr (C::ALDS) {
 #pragma unroll
         for (int i = 0; i < NAT; ++i) {
             const int e = tid + i * NT;
@@ -679,48 +753,7 @@ __device__ __forceinline__ void mfma2d_rows_tile(const Mfma2DArgs &a, const int 
         }
     }
     __syncthreads();
-
-    ACC acc[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = ACC{};
-    const int colw = 16 * wave + 8 * lg;
-#pragma unroll
-    for (int ar = -R; ar <= R; ++ar) {
-        if (band_amax(SHAPE, r, T, 0, ar) < 0) continue;
-        const int klo = rows_kk_lo(SHAPE, r, T, ar), nb = rows_nblk(SHAPE, r, T, ar);
-        const int off = rows_frag_offset(SHAPE, r, T, ar);
-#pragma unroll
-        for (int ib = 0; ib < nb; ++ib) {
-            const FR A = ALDS ? lA[(off + ib) * 64 + lane] : afr[(off + ib) * 64 + lane];
-            const int col = colw + 32 * (klo + ib);
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const FR B = *reinterpret_cast<const FR *>(&lb[(16 * v + ln + ar + R) * PIT + col]);
-                acc[v] = mfma16(A, B, acc[v]);
-            }
-        }
-    }
-
-    // ---- store: lane (lg, ln) holds row r0 + 16 v + ln, columns 4 lg .. 4 lg + 3
-    TS *dst = static_cast<TS *>(a.dst);
-    const int gc = c0 + 16 * wave + 4 * lg;
-    const bool vec = gc + 4 <= n1 && (n1 % 4) == 0 && (reinterpret_cast<uintptr_t>(dst) % 8) == 0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int gr = r0 + 16 * v + ln;
-        if (gr >= n0 || gc >= n1) continue;
-        TS *p = dst + (int64_t)gr * n1 + gc;
-        if (vec) {
-            RawVec<TS, 4> ov;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) ov.e[e] = to_storage<TS>(acc[v][e]);
-            ov.store(p);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (gc + e < n1) p[e] = to_storage<TS>(acc[v][e]);
-        }
-    }
+    C::compute_store(a, tile, lb, lA, tid);
 }
 
 // The 16-bit dense kernels use the row layout when its operand table fits
@@ -805,8 +838,8 @@ hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
     Mfma2DArgs a;
     if (!mfma2d_args<DT, SHAPE, r, T>(p, &a)) return hipErrorInvalidValue;
     if (a.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW, SP>), dim3(a.ntiles), dim3(64 * NW), 0,
-                       stream, a);
+    hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW, SP>), dim3(a.ntiles), dim3(64 * NW), 0, stream,
+                       a);
     return hipGetLastError();
 }
 
