@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--only", default="", help="comma list of headline variant names to run")
     ap.add_argument("--sections", default="c2,c3,c4,c5,cases,sparse,grid,seq")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-clocks", action="store_true",
+                    help="skip the rocm-smi clock reading (runs under a profiler, which may not start "
+                         "other programs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jobs", type=int, default=4096, help="served-stream jobs")
     ap.add_argument("--calib-copy", action="store_true",
@@ -892,7 +895,7 @@ def main():
     head_name = max(pool, key=lambda k: pool[k]["gst"]) if pool else None
     hv = next((v for v in headline_variants(args.n, args.time_steps) if v["name"] == head_name), None)
     clocks = None
-    if hv:
+    if hv and not args.no_clocks:
         clocks = headline_clocks(stl, args, hv)
     c3 = section_c3(stl, args) if "c3" in sections else {}
     c4 = section_c4(stl, args) if "c4" in sections else None
