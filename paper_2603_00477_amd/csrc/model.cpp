@@ -105,10 +105,10 @@ static double valu_halo_factor(int shape, int d, int r, int T, int dtype)
     }
     if (T == 1) return 1.0;
     // fused 3D passes: every step computes the L1 x M1 layout (2 rows x W
-    // columns per thread, 16 x 32 threads for stars, 16 x 16 for boxes); the
-    // input halo is staged, so the output tile is the layout less r (T - 1)
-    // per side, the left margin rounded up to a whole vector
-    const int L1 = 2 * (shape == STENCIL_STAR ? 32 : 16), M1 = 16 * W;
+    // columns per thread; stars 16 x 32 threads, boxes 32 rows x 64 columns);
+    // the input halo is staged, so the output tile is the layout less
+    // r (T - 1) per side, the left margin rounded up to a whole vector
+    const int L1 = 2 * (shape == STENCIL_STAR ? 32 : 16), M1 = shape == STENCIL_STAR ? 16 * W : 64;
     const int SK = r * (T - 1), SKL = (SK + W - 1) / W * W;
     const int BY = L1 - 2 * SK, BX = (M1 - SKL - SK) / W * W;
     if (BY <= 0 || BX <= 0) return 0.0;

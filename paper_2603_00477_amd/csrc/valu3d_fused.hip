@@ -539,13 +539,16 @@ hipError_t launch_fused3d_batch_cfg(const PassArgs *ps, int n, BatchStaging *sta
 // rows per thread.  Stars take 16 x 32 threads (a 64-row layout: the skirt is
 // a smaller share of it); measured on 512^3 against 16 x 16, Star-3D2R float32
 // T = 3 runs at 959 vs 517 GSt/s and Star-3D3R float64 T = 2 at 323 vs 281.
-// The 27-point box keeps 16 x 16 (Box-3D1R float32 T = 2: 601 vs 574), where
-// two resident workgroups per CU matter more than the smaller skirt.
+// The 27-point box takes a 32-row x 64-column layout: 16 x 16 threads in
+// float32 (Box-3D1R T = 2: 601 vs 574 GSt/s with 32 thread rows; two resident
+// workgroups per CU matter more than a smaller skirt), 32 x 16 in float64
+// (406 vs 374 against 16 x 16: 512 columns take 9 output tiles of 60 instead
+// of 19 of 28).
 template <typename TS, int SHAPE, int R, int T>
 struct Fused3DShape {
     static constexpr int W = sizeof(TS) == 8 ? 2 : 4;
     static constexpr int WY = 2;
-    static constexpr int TX = 16;
+    static constexpr int TX = SHAPE == STENCIL_STAR ? 16 : 64 / W;
     static constexpr int TY = SHAPE == STENCIL_STAR ? 32 : 16;
     static constexpr int PF = 1;
 };

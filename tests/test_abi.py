@@ -221,7 +221,7 @@ def test_halo_model_terms():
     assert stl.model_predict("star", 3, 2, 1, "f32")["halo_valu"] == 1.0
     # 3D fused passes stage the input halo: float32 Star-3D2R T = 2 computes a
     # 64 x 64 layout for a 60 x 56 output tile (margin 2, left margin rounded
-    # up to a 4-column vector); float64 Box-3D1R T = 2 a 32 x 32 layout for 30 x 28
+    # up to a 4-column vector); float64 Box-3D1R T = 2 a 32 x 64 layout for 30 x 60
     assert stl.model_predict("star", 3, 2, 2, "f32")["halo_valu"] == pytest.approx(4096 / (60 * 56))
-    assert stl.model_predict("box", 3, 1, 2, "f64")["halo_valu"] == pytest.approx(1024 / (30 * 28))
+    assert stl.model_predict("box", 3, 1, 2, "f64")["halo_valu"] == pytest.approx(2048 / (30 * 60))
     assert stl.kernel_available("mfma_seq", "bf16", "box", 2, 2, 4)
