@@ -158,3 +158,23 @@ def test_json_line_is_small_and_complete():
     assert line["summary"]["model_check"] == "36/36"
     assert len(line["summary"]["precision"]["bf16-mfma-T4"]) == 3
     assert line["summary"]["serving"]["served"] == [5.03, 106.09, 138.1]
+
+
+def test_case_names_and_the_measured_ceiling_column():
+    """Variant names parse into (shape, d, r, dtype, T); the model's second
+    column takes per-dtype ceilings and changes the verdict only through them:
+    with the datasheet ceilings it equals the first column, and with a vector
+    unit far slower than the matrix unit the MFMA path wins."""
+    import paper_2603_00477_amd as stl
+    assert bench.parse_case("box-2d3r-f64-T2") == ("box", 2, 3, "f64", 2)
+    assert bench.parse_case("star-3d2r-f32-T3-valu") == ("star", 3, 2, "f32", 3)
+    assert bench.parse_case("no such case") is None
+    dt = "f64"
+    datasheet = stl.hw_default(dt) if hasattr(stl, "hw_default") else None
+    if datasheet is not None:
+        hw = {"per_dtype": {dt: datasheet}}
+        m = stl.model_predict("box", 2, 3, 2, dt)
+        assert bench.predicted_with(stl, hw, "box-2d3r-f64-T2") == {-1: "valu", 0: "tie", 1: "mfma"}[m["winner"]]
+    slow_valu = {"per_dtype": {dt: dict(BB=8e12, PP_valu=1e11, PP_mfma=78.6e12, PP_mfma_sparse=157.2e12)}}
+    assert bench.predicted_with(stl, slow_valu, "box-2d3r-f64-T1") == "mfma"
+    assert bench.predicted_with(stl, None, "box-2d3r-f64-T1") is None
