@@ -48,7 +48,7 @@ struct Fused3DArgs {
     TC w[K];
 };
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 struct Fused3DCfg {
     static constexpr int K = SHAPE == STENCIL_BOX ? (2 * R + 1) * (2 * R + 1) * (2 * R + 1) : 6 * R + 1;
     static constexpr int NT = TX * TY;
@@ -70,7 +70,6 @@ struct Fused3DCfg {
     // FMAs with a scalar operand issue slower on gfx950)
     static constexpr int WMODE = (sizeof(TC) * K <= 192 && (sizeof(TC) == 8 || R >= 3)) ? 0 : 1;
     static_assert(BY > 0 && BX > 0, "layout narrower than the fused margin");
-    static_assert(PF == 1 || PF == Q, "prefetch distance is one plane or 2R+1 planes");
     static_assert(sizeof(TC) * K <= 256, "large boxes run on the one-step box kernel");
 };
 
@@ -92,12 +91,12 @@ __device__ __forceinline__ int star3f_index(int axis, int off)
     return 1 + axis * 2 * R + (off < 0 ? off + R : off + R - 1);
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF, bool FAST>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, bool FAST>
 __device__ __forceinline__ void fused3d_tile(
-    const Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>::K> &a, const int tile,
-    TC (&lds)[T][2][Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>::PLANE])
+    const Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> &a, const int tile,
+    TC (&lds)[T][2][Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::PLANE])
 {
-    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>;
+    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
     constexpr int K = Cfg::K, Q = Cfg::Q, NT = Cfg::NT, LDX = Cfg::LDX, PLANE = Cfg::PLANE;
     constexpr int NS = Cfg::NS, NV = Cfg::NV, SK = Cfg::SK, SKL = Cfg::SKL, OX = Cfg::OX;
     using Vec = RawVec<TS, W>;
@@ -245,10 +244,10 @@ __device__ __forceinline__ void fused3d_tile(
 #pragma unroll
                     for (int j = 0; j < W; ++j) acc[s][q][i][j] = TC(0);
 
-        Vec ring[PF][NS];
-#pragma unroll
-        for (int u = 0; u < PF; ++u)
-            if (u < KTOT) load_plane(u, ring[u]);
+        // prefetch of the next plane (one plane ahead: the plane's compute
+        // covers the load latency, and a deeper ring costs registers)
+        Vec ring[NS];
+        load_plane(0, ring);
         __syncthreads();
 
         for (int kb = 0; kb < KTOT; kb += Q) {
@@ -258,11 +257,10 @@ __device__ __forceinline__ void fused3d_tile(
                 if (k >= KTOT) break;
                 const int par = k & 1;
                 {
-                    const int slot = PF == 1 ? 0 : u;
-                    stage_plane(k, ring[slot], &lds[0][par][0]);
+                    stage_plane(k, ring, &lds[0][par][0]);
                     // keep the refill of the ring behind the writes that drain it
                     __builtin_amdgcn_sched_barrier(0);
-                    if (k + PF < KTOT) load_plane(k + PF, ring[slot]);
+                    if (k + 1 < KTOT) load_plane(k + 1, ring);
                 }
 #pragma unroll
                 for (int s = 1; s <= T; ++s) {
@@ -378,28 +376,28 @@ __device__ __forceinline__ bool fused3d_fast(const A &a, int tile, int BX)
     return vec_aligned<TS, W>(a.src, a.n2, 0) && (x0 % W) == 0;
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void fused3d_kernel(
-    Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>::K> a)
+    Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> a)
 {
-    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>;
+    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
     __shared__ __attribute__((aligned(16))) TC lds[T][2][Cfg::PLANE];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= a.ntiles) return;
     if (fused3d_fast<TS, W>(a, tile, Cfg::BX))
-        fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF, true>(a, tile, lds);
+        fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, true>(a, tile, lds);
     else
-        fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF, false>(a, tile, lds);
+        fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, false>(a, tile, lds);
 }
 
 // Persistent batched launch over the tiles of every job of the batch (see the
 // one-step 3D kernel); the tile body ends with a barrier.
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void fused3d_batch_kernel(
-    const Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>::K> *__restrict__ jobs,
+    const Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> *__restrict__ jobs,
     const int *__restrict__ tile_start, int njobs)
 {
-    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>;
+    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
     __shared__ __attribute__((aligned(16))) TC lds[T][2][Cfg::PLANE];
     const int total = tile_start[njobs];
     int j = 0;
@@ -408,9 +406,9 @@ __global__ __launch_bounds__(TX *TY) void fused3d_batch_kernel(
         const Fused3DArgs<TC, Cfg::K> a = jobs[j];
         const int tile = item - tile_start[j];
         if (fused3d_fast<TS, W>(a, tile, Cfg::BX))
-            fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF, true>(a, tile, lds);
+            fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, true>(a, tile, lds);
         else
-            fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF, false>(a, tile, lds);
+            fused3d_tile<TS, TC, SHAPE, R, T, W, WY, TX, TY, false>(a, tile, lds);
     }
 }
 
@@ -437,11 +435,11 @@ inline int fused3d_segments(int D0, int inplane, int slots, int R, int T)
     return best;
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 bool fused3d_args(const PassArgs &p, int slots,
-                  Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>::K> *out, hipError_t *err)
+                  Fused3DArgs<TC, Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>::K> *out, hipError_t *err)
 {
-    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>;
+    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
     *err = hipSuccess;
     Fused3DArgs<TC, Cfg::K> &a = *out;
     a.src = p.src;
@@ -487,26 +485,26 @@ int fused3d_slots(K kernel, int threads, int num_cu)
     return occ * (num_cu > 0 ? num_cu : 256);
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 hipError_t launch_fused3d_cfg(const PassArgs &p, hipStream_t stream)
 {
-    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>;
-    static const int slots = fused3d_slots(fused3d_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>, TX * TY,
+    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
+    static const int slots = fused3d_slots(fused3d_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>, TX * TY,
                                            p.num_cu);
     Fused3DArgs<TC, Cfg::K> a;
     hipError_t err;
-    if (!fused3d_args<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>(p, slots, &a, &err)) return err;
-    hipLaunchKernelGGL((fused3d_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>), dim3(a.ntiles), dim3(TX * TY), 0,
+    if (!fused3d_args<TS, TC, SHAPE, R, T, W, WY, TX, TY>(p, slots, &a, &err)) return err;
+    hipLaunchKernelGGL((fused3d_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>), dim3(a.ntiles), dim3(TX * TY), 0,
                        stream, a);
     return hipGetLastError();
 }
 
-template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY, int PF>
+template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 hipError_t launch_fused3d_batch_cfg(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
-    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>;
+    using Cfg = Fused3DCfg<TS, TC, SHAPE, R, T, W, WY, TX, TY>;
     using Args = Fused3DArgs<TC, Cfg::K>;
-    static const int slots = fused3d_slots(fused3d_batch_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>,
+    static const int slots = fused3d_slots(fused3d_batch_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>,
                                            TX * TY, ps[0].num_cu);
     std::vector<Args> jobs;
     std::vector<int> start(1, 0);
@@ -514,7 +512,7 @@ hipError_t launch_fused3d_batch_cfg(const PassArgs *ps, int n, BatchStaging *sta
     for (int i = 0; i < n; ++i) {
         Args a;
         hipError_t err;
-        if (!fused3d_args<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>(ps[i], slots, &a, &err)) {
+        if (!fused3d_args<TS, TC, SHAPE, R, T, W, WY, TX, TY>(ps[i], slots, &a, &err)) {
             if (err != hipSuccess) return err;
             continue;
         }
@@ -528,13 +526,12 @@ hipError_t launch_fused3d_batch_cfg(const PassArgs *ps, int n, BatchStaging *sta
                                    stream);
     if (e != hipSuccess) return e;
     const int total = start.back();
-    hipLaunchKernelGGL((fused3d_batch_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY, PF>),
+    hipLaunchKernelGGL((fused3d_batch_kernel<TS, TC, SHAPE, R, T, W, WY, TX, TY>),
                        dim3(total < slots ? total : slots), dim3(TX * TY), 0, stream,
                        static_cast<const Args *>(djobs), static_cast<const int *>(dstart), (int)jobs.size());
     return hipGetLastError();
 }
 
-#ifndef F3_SHAPE_OVERRIDE
 // Thread layouts: W consecutive columns per thread (float64 2, float32 4), 2
 // rows per thread.  Stars take 16 x 32 threads (a 64-row layout: the skirt is
 // a smaller share of it); measured on 512^3 against 16 x 16, Star-3D2R float32
@@ -550,24 +547,20 @@ struct Fused3DShape {
     static constexpr int WY = 2;
     static constexpr int TX = SHAPE == STENCIL_STAR ? 16 : 64 / W;
     static constexpr int TY = SHAPE == STENCIL_STAR ? 32 : 16;
-    static constexpr int PF = 1;
 };
-#else
-F3_SHAPE_OVERRIDE
-#endif
 
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_fused3d(const PassArgs &p, hipStream_t stream)
 {
     using S = Fused3DShape<TS, SHAPE, R, T>;
-    return launch_fused3d_cfg<TS, TC, SHAPE, R, T, S::W, S::WY, S::TX, S::TY, S::PF>(p, stream);
+    return launch_fused3d_cfg<TS, TC, SHAPE, R, T, S::W, S::WY, S::TX, S::TY>(p, stream);
 }
 
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_fused3d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
     using S = Fused3DShape<TS, SHAPE, R, T>;
-    return launch_fused3d_batch_cfg<TS, TC, SHAPE, R, T, S::W, S::WY, S::TX, S::TY, S::PF>(ps, n, stage, stream);
+    return launch_fused3d_batch_cfg<TS, TC, SHAPE, R, T, S::W, S::WY, S::TX, S::TY>(ps, n, stage, stream);
 }
 
 #define F3(TS, TC, DT, SH, R, T) \
