@@ -414,13 +414,18 @@ __global__ __launch_bounds__(TX *TY) void fused3d_batch_kernel(
 
 // Segment length along z: the number of segments maximises (share of the
 // resident slots the last round keeps busy) x (share of staged planes that
-// are outputs, BZ / (BZ + 2 R T)).
+// are outputs, BZ / (BZ + 2 R T)), with segments of at least max(8 R T, 32)
+// planes (or the whole grid): shorter ones restage and recompute their
+// 2 R T + T lead-in planes too often, which a batched launch of many small
+// grids does not need to fill the GPU.
 inline int fused3d_segments(int D0, int inplane, int slots, int R, int T)
 {
+    const int minBZ = 8 * R * T > 32 ? 8 * R * T : 32;
     int best = 1;
     double best_score = -1.0;
     for (int segs = 1; segs <= 256 && segs <= D0; ++segs) {
         const int BZ = (D0 + segs - 1) / segs;
+        if (segs > 1 && BZ < minBZ) break;
         const int nzs = (D0 + BZ - 1) / BZ;
         const int64_t items = (int64_t)nzs * inplane;
         const int64_t rounds = (items + slots - 1) / slots;
