@@ -97,8 +97,9 @@ static double valu_halo_factor(int shape, int d, int r, int T, int dtype)
 {
     const int D = dtype_bytes(dtype);
     const int W16 = 16 / D > 8 ? 8 : 16 / D;
-    // columns per lane of the 2D kernel: one 16-byte vector, two for float64 at T = 2
-    const int W = (d == 2 && D == 8 && T == 2) ? 2 * W16 : W16;
+    // columns per lane of the 2D kernel: one 16-byte vector, two for float64
+    // at T = 2 and for float64 r = 7 at T = 1
+    const int W = (d == 2 && D == 8 && (T == 2 || (T == 1 && r >= 7))) ? 2 * W16 : W16;
     if (d == 2) {
         const int E = (r * T + W - 1) / W * W;
         return (64.0 * W) / (64.0 * W - 2.0 * E);

@@ -554,17 +554,22 @@ __global__ __launch_bounds__(64 * kValu2DWaves) void valu2d_batch_kernel(
 // Columns per lane: one 16-byte vector, except float64 at T = 2, which takes
 // two (256-column bands: the 2E-column skirt is half the share of the band;
 // Box-2D3R 8192^2: 368 vs 345 GSt/s, Star-2D3R: 580 vs 528).  At T = 1 and
-// T >= 3 the 2-column lanes measured faster (occupancy).
-template <typename TS, int T>
+// T >= 3 the 2-column lanes measured faster (occupancy), except for the
+// compute-bound float64 r = 7 passes, whose 8-column skirt is then half the
+// share of the band (10240^2 T = 1: Star-2D7R 260 -> 297, Box-2D7R 95 -> 101
+// GSt/s; memory-bound r <= 3 one-step passes 3-10 % slower with 4 columns).
+template <typename TS, int R, int T>
 struct Valu2DShape {
-    static constexpr int W = (sizeof(TS) == 8 && T == 2) ? 4 : (16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS));
+    static constexpr int W = (sizeof(TS) == 8 && (T == 2 || (T == 1 && R >= 7)))
+                                 ? 4
+                                 : (16 / sizeof(TS) > 8 ? 8 : 16 / sizeof(TS));
 };
 
 // Fill the geometry of one pass; returns false when there is nothing to do.
 template <typename TS, typename TC, int SHAPE, int R, int T>
 bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
 {
-    using S = Valu2DShape<TS, T>;
+    using S = Valu2DShape<TS, R, T>;
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     *err = hipSuccess;
     g->src = p.src;
@@ -611,7 +616,7 @@ bool valu2d_geometry(const PassArgs &p, Valu2DJob<TC> *g, hipError_t *err)
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
 {
-    using S = Valu2DShape<TS, T>;
+    using S = Valu2DShape<TS, R, T>;
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     Valu2DArgs<TC, Cfg::K> a;
     hipError_t err;
@@ -636,7 +641,7 @@ hipError_t launch_valu2d(const PassArgs &p, hipStream_t stream)
 template <typename TS, typename TC, int SHAPE, int R, int T>
 hipError_t launch_valu2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
-    using S = Valu2DShape<TS, T>;
+    using S = Valu2DShape<TS, R, T>;
     using Cfg = Valu2DCfg<TS, TC, SHAPE, R, T, S::W>;
     using Job = Valu2DBatchJob<TC, Cfg::K>;
     std::vector<Job> jobs;

@@ -217,6 +217,8 @@ def test_halo_model_terms():
     assert m["halo_valu"] == pytest.approx(256 / 240)
     # (the skirt rounds up to whole 16-byte vectors: 3 -> 4 columns)
     assert stl.model_predict("box", 2, 3, 1, "f64")["halo_valu"] == pytest.approx(128 / 120)
+    # float64 r = 7 one-step passes run 4-column lanes: 256-column bands, 8-column skirts
+    assert stl.model_predict("star", 2, 7, 1, "f64")["halo_valu"] == pytest.approx(256 / 240)
     # 3D one-step passes stage their halo: no skirt
     assert stl.model_predict("star", 3, 2, 1, "f32")["halo_valu"] == 1.0
     # 3D fused passes stage the input halo: float32 Star-3D2R T = 2 computes a
