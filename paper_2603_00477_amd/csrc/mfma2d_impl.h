@@ -596,7 +596,12 @@ struct RowsCfg {
     static constexpr int KMAX = 16 * (NW - 1) + 32 * NKB0;                  // frame columns read
     static constexpr int LCD = TC + 2 * R + DL;                             // frame columns holding data
     static constexpr int LCF = ((KMAX > LCD ? KMAX : LCD) + 7) / 8 * 8;     // staged columns
-    static constexpr int PIT = (LCF / 8) % 2 ? LCF : LCF + 8;               // odd number of 16-byte units per row
+    // row pitch in 16-byte units: 2 mod 4 for eight-wave tiles, odd for
+    // four-wave ones (measured on 16384^2: bf16 Box-2D2R T = 4 2766 -> 2968,
+    // Star-2D2R T = 4 2839 -> 3075 GSt/s with 2 mod 4; the four-wave tiles
+    // at T = 1, 2 are 1-2 % faster with an odd pitch)
+    static constexpr int PIT = NW == 8 ? LCF + 8 * ((2 - (LCF / 8) % 4 + 4) % 4)
+                                       : ((LCF / 8) % 2 ? LCF : LCF + 8);
     static constexpr int NFRAG = rows_total_frags(SHAPE, r, T);
     static constexpr bool ALDS = NFRAG <= 24;
     static constexpr int NCH = LCF / 8;                                     // 16-byte chunks per frame row
