@@ -154,7 +154,7 @@ struct Mfma2DArgs {
     double h;
 };
 
-template <int DT, int SHAPE, int r, int T, int V, int NW>
+template <int DT, int SHAPE, int r, int T, int V, int NW, bool SP = false>
 struct Mfma2DCfg {
     using MT = MfmaTypes<DT>;
     static constexpr int KDIM = MT::KDIM;
@@ -167,11 +167,15 @@ struct Mfma2DCfg {
     static constexpr int KKH = band_kk_hi(SHAPE, r, T, 0, 0, KDIM);
     static constexpr int LRK = 16 * (V - 1) + KDIM * (KKH + 1);  // rows an operand may touch
     static constexpr int LR0 = LRD > LRK ? LRD : LRK;
-    // column-major blocks (16-bit operands): an odd number of 16-byte units
-    // per column, so the 16 columns one B-fragment read touches fall in
-    // distinct bank groups
+    // column-major blocks (16-bit operands): the column pitch in 16-byte
+    // units is 2 mod 4 for the dense kernels and odd for the 2:4 sparse one
+    // (measured against the other parity: compensated bf16x3 Box-2D2R T = 4
+    // 16384^2 1186 -> 1229, bf16 Box-2D3R T = 4 8192^2 1390 -> 1443 GSt/s;
+    // the sparse kernel 23-32 % slower with 2 mod 4)
     static constexpr int LR8 = ((LR0 + 7) / 8) * 8;
-    static constexpr int LR = LR8 + (KDIM != 4 && (LR8 / 8) % 2 == 0 ? 8 : 0);
+    static constexpr int LR = KDIM == 4 ? LR8
+                              : SP      ? LR8 + ((LR8 / 8) % 2 == 0 ? 8 : 0)
+                                        : LR8 + 8 * ((2 - (LR8 / 8) % 4 + 4) % 4);
     // row-major pitch (KDIM = 4) padded off multiples of the bank count
     static constexpr int LCP = LC + ((LC % 32) == 0 ? 1 : 0);
     static constexpr int LDS_ELEMS = KDIM == 4 ? LR * LCP : LC * LR;
@@ -213,7 +217,7 @@ struct BandCols {
 template <int DT, int SHAPE, int r, int T, int V, int NW, bool SP = false>
 __device__ __forceinline__ void mfma2d_tile(const Mfma2DArgs &a, const int tile)
 {
-    using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
+    using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW, SP>;
     using MT = typename Cfg::MT;
     using TS = typename MT::TS;
     using OP = typename MT::OP;
