@@ -600,10 +600,10 @@ struct RowsCfg {
     static constexpr int KMAX = 16 * (NW - 1) + 32 * NKB0;                  // frame columns read
     static constexpr int LCD = TC + 2 * R + DL;                             // frame columns holding data
     static constexpr int LCF = ((KMAX > LCD ? KMAX : LCD) + 7) / 8 * 8;     // staged columns
-    // row pitch in 16-byte units: 2 mod 4 for eight-wave tiles, odd for
-    // four-wave ones (measured on 16384^2: bf16 Box-2D2R T = 4 2766 -> 2968,
-    // Star-2D2R T = 4 2839 -> 3075 GSt/s with 2 mod 4; the four-wave tiles
-    // at T = 1, 2 are 1-2 % faster with an odd pitch)
+    // row pitch in 16-byte units: 2 mod 4 for eight-wave tiles, which makes
+    // the operand-B reads conflict-free (measured on 16384^2: bf16 Box-2D2R
+    // T = 4 2766 -> 2968, Star-2D2R T = 4 2839 -> 3075 GSt/s against an odd
+    // pitch); odd for four-wave tiles (1-2 % faster there than the others)
     static constexpr int PIT = NW == 8 ? LCF + 8 * ((2 - (LCF / 8) % 4 + 4) % 4)
                                        : ((LCF / 8) % 2 ? LCF : LCF + 8);
     static constexpr int NFRAG = rows_total_frags(SHAPE, r, T);
@@ -808,14 +808,16 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs 
     }
 }
 
-// 16-bit storage with composite radius >= 6: eight waves side by side (64 x
-// 128 workgroup tiles, a smaller halo share) measured 5-18 % faster on
-// 16384^2; smaller radii and the compensated mode keep four (up to 12 %
-// slower with eight).
+// Dense 16-bit storage: eight waves side by side (64 x 128 workgroup tiles,
+// a smaller halo share).  With the conflict-free row pitch of these tiles
+// they measured faster at every depth on 16384^2 (bf16 Box-2D2R T = 1 / 2 /
+// 4: 856 -> 949, 1644 -> 1814, 2766 -> 2978 GSt/s; Box-2D1R T = 1 848 ->
+// 987); with an odd pitch, small composite radii had been up to 12 % slower
+// with eight.  The compensated mode keeps four.
 template <int DT, int r, int T>
 struct Mfma2DShape {
     static constexpr int V = 4;
-    static constexpr int NW = (MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3 && r * T >= 6) ? 8 : 4;
+    static constexpr int NW = (MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3) ? 8 : 4;
 };
 
 template <int DT, int SHAPE, int r, int T>
