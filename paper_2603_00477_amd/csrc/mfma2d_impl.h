@@ -808,16 +808,17 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs 
     }
 }
 
-// Dense 16-bit storage: eight waves side by side (64 x 128 workgroup tiles,
+// 16-bit operands: eight waves side by side (64 x 128 workgroup tiles,
 // a smaller halo share).  With the conflict-free row pitch of these tiles
 // they measured faster at every depth on 16384^2 (bf16 Box-2D2R T = 1 / 2 /
 // 4: 856 -> 949, 1644 -> 1814, 2766 -> 2978 GSt/s; Box-2D1R T = 1 848 ->
 // 987); with an odd pitch, small composite radii had been up to 12 % slower
-// with eight.  The compensated mode keeps four.
+// with eight.  The compensated mode's column-layout tiles gain too (bf16x3
+// Box-2D2R T = 2 / 4: 886 -> 974, 1211 -> 1272 GSt/s).
 template <int DT, int r, int T>
 struct Mfma2DShape {
     static constexpr int V = 4;
-    static constexpr int NW = (MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3) ? 8 : 4;
+    static constexpr int NW = MfmaTypes<DT>::KDIM == 32 ? 8 : 4;
 };
 
 template <int DT, int SHAPE, int r, int T>
