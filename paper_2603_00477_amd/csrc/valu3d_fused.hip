@@ -48,6 +48,15 @@ struct Fused3DArgs {
     TC w[K];
 };
 
+// value of v in lane (lane - 1) (PREV) or (lane + 1) of the same 16-lane
+// row; the row's first (PREV) or last lane receives `edge`
+template <bool PREV>
+__device__ __forceinline__ float lane_row_shift(float v, float edge)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), PREV ? 0x111 : 0x101,
+                                                      0xF, 0xF, false));
+}
+
 template <typename TS, typename TC, int SHAPE, int R, int T, int W, int WY, int TX, int TY>
 struct Fused3DCfg {
     static constexpr int K = SHAPE == STENCIL_BOX ? (2 * R + 1) * (2 * R + 1) * (2 * R + 1) : 6 * R + 1;
@@ -198,6 +207,18 @@ __device__ __forceinline__ void fused3d_tile(
     const bool dst_vec = vec_aligned<TS, W>(dst, n2, x0);
     // LDS offset of this thread's first point inside a plane
     const int lpos = (R + ty * WY) * LDX + OX + tx * W;
+    // Window edges from the neighbouring lane.  Each lane's single-element
+    // reads of the r columns left and right of its vector all fall in banks
+    // of one residue mod 4 (the row pitch keeps the vectors aligned), a 4-way
+    // conflict.  With rows of 16 threads (one DPP row each) the edges are
+    // the neighbours' own elements: a row shift by one lane, the first and
+    // last lanes of the row taking the LDS value instead; the other lanes
+    // read a dummy element of their own vector, spread over the banks.
+    // Measured on 512^3 float32: Box-3D1R T = 2 / 3 600 -> 651, 642 -> 726,
+    // Star-3D3R T = 2 518 -> 553 GSt/s; Star-3D2R 5-10 % slower (stars need
+    // edges on their middle rows only), Star-3D1R unchanged.
+    constexpr bool XDPP = TX == 16 && R <= W && sizeof(TC) == 4 && (SHAPE == STENCIL_BOX || R >= 3);
+    const int dj = R + ((tx + ty) & (W - 1));
 
     {
         auto load_plane = [&](int k, Vec (&v)[NS]) {
@@ -272,10 +293,29 @@ __device__ __forceinline__ void fused3d_tile(
                         for (int wi = 0; wi < WY + 2 * R; ++wi) {
                             const bool mid = wi >= R && wi < R + WY;
                             TC row[W + 2 * R];
+                            if constexpr (XDPP) {
 #pragma unroll
-                            for (int j = 0; j < W + 2 * R; ++j) {
-                                const bool need = SHAPE == STENCIL_BOX || mid || (j >= R && j < R + W);
-                                row[j] = need ? rb[wi * LDX + j] : TC(0);
+                                for (int j = 0; j < W; ++j) row[R + j] = rb[wi * LDX + R + j];
+#pragma unroll
+                                for (int j = 0; j < R; ++j) {
+                                    row[j] = TC(0);
+                                    row[R + W + j] = TC(0);
+                                }
+                                if (SHAPE == STENCIL_BOX || mid) {
+#pragma unroll
+                                    for (int m = 0; m < R; ++m) {
+                                        const TC lt = rb[wi * LDX + (tx == 0 ? m : dj)];
+                                        const TC rt = rb[wi * LDX + (tx == TX - 1 ? R + W + m : dj)];
+                                        row[m] = lane_row_shift<true>(row[W + m], lt);
+                                        row[R + W + m] = lane_row_shift<false>(row[R + m], rt);
+                                    }
+                                }
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < W + 2 * R; ++j) {
+                                    const bool need = SHAPE == STENCIL_BOX || mid || (j >= R && j < R + W);
+                                    row[j] = need ? rb[wi * LDX + j] : TC(0);
+                                }
                             }
 #pragma unroll
                             for (int c = -R; c <= R; ++c) {
