@@ -814,17 +814,23 @@ __global__ __launch_bounds__(64 * NW) void mfma2d_batch_kernel(const Mfma2DArgs 
 // 4: 856 -> 949, 1644 -> 1814, 2766 -> 2978 GSt/s; Box-2D1R T = 1 848 ->
 // 987); with an odd pitch, small composite radii had been up to 12 % slower
 // with eight.  The compensated mode's column-layout tiles gain too (bf16x3
-// Box-2D2R T = 2 / 4: 886 -> 974, 1211 -> 1272 GSt/s).
-template <int DT, int r, int T>
+// Box-2D2R T = 2 / 4: 886 -> 974, 1211 -> 1272 GSt/s).  Dense (not 2:4
+// sparse) 16-bit
+// passes with r <= 2 and composite radius 2-4 stack six tiles per wave (96 x
+// 128: fewer halo rows per output row; +0.5-3 % measured, e.g. Star-2D2R
+// T = 2 1806 -> 1858, Box-2D1R T = 4 3610 -> 3696 GSt/s); Box-2D3R T = 1
+// was 8 % slower with six.
+template <int DT, int r, int T, bool SP = false>
 struct Mfma2DShape {
-    static constexpr int V = 4;
+    static constexpr int V =
+        (MfmaTypes<DT>::KDIM == 32 && !MfmaTypes<DT>::X3 && !SP && r <= 2 && r * T >= 2 && r * T <= 4) ? 6 : 4;
     static constexpr int NW = MfmaTypes<DT>::KDIM == 32 ? 8 : 4;
 };
 
-template <int DT, int SHAPE, int r, int T>
+template <int DT, int SHAPE, int r, int T, bool SP = false>
 bool mfma2d_args(const PassArgs &p, Mfma2DArgs *out)
 {
-    constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
+    constexpr int V = Mfma2DShape<DT, r, T, SP>::V, NW = Mfma2DShape<DT, r, T, SP>::NW;
     using Cfg = Mfma2DCfg<DT, SHAPE, r, T, V, NW>;
     if (p.steps != T || !p.afrag) return false;
     if (MfmaTypes<DT>::X3 && !p.afrag_lo) return false;
@@ -846,9 +852,9 @@ bool mfma2d_args(const PassArgs &p, Mfma2DArgs *out)
 template <int DT, int SHAPE, int r, int T, bool SP = false>
 hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
 {
-    constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
+    constexpr int V = Mfma2DShape<DT, r, T, SP>::V, NW = Mfma2DShape<DT, r, T, SP>::NW;
     Mfma2DArgs a;
-    if (!mfma2d_args<DT, SHAPE, r, T>(p, &a)) return hipErrorInvalidValue;
+    if (!mfma2d_args<DT, SHAPE, r, T, SP>(p, &a)) return hipErrorInvalidValue;
     if (a.ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL((mfma2d_kernel<DT, SHAPE, r, T, V, NW, SP>), dim3(a.ntiles), dim3(64 * NW), 0, stream,
                        a);
@@ -859,13 +865,13 @@ hipError_t launch_mfma2d(const PassArgs &p, hipStream_t stream)
 template <int DT, int SHAPE, int r, int T, bool SP = false>
 hipError_t launch_mfma2d_batch(const PassArgs *ps, int n, BatchStaging *stage, hipStream_t stream)
 {
-    constexpr int V = Mfma2DShape<DT, r, T>::V, NW = Mfma2DShape<DT, r, T>::NW;
+    constexpr int V = Mfma2DShape<DT, r, T, SP>::V, NW = Mfma2DShape<DT, r, T, SP>::NW;
     std::vector<Mfma2DArgs> jobs;
     std::vector<int> start(1, 0);
     jobs.reserve(n);
     for (int i = 0; i < n; ++i) {
         Mfma2DArgs a;
-        if (!mfma2d_args<DT, SHAPE, r, T>(ps[i], &a)) return hipErrorInvalidValue;
+        if (!mfma2d_args<DT, SHAPE, r, T, SP>(ps[i], &a)) return hipErrorInvalidValue;
         if (a.ntiles <= 0) continue;
         if ((int64_t)start.back() + a.ntiles > (1LL << 30)) return hipErrorInvalidValue;
         jobs.push_back(a);
