@@ -200,6 +200,16 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
         col_store[j] = c >= x0 && c < xe;
     }
     const bool vec_ok = vec_aligned<TS, W>(src, n1, cb) && cb >= 0 && cb + W <= n1;
+    // output stores: the whole vector, or (lanes at the band's ragged edge)
+    // element by element; the element path is skipped by a wave-uniform
+    // branch when no lane of the wave needs it
+    bool st_all = vec_ok, st_any = false;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        st_all = st_all && col_store[j];
+        st_any = st_any || col_store[j];
+    }
+    const bool st_part_wave = __ballot(st_any && !st_all) != 0;
     const TS hs = to_storage<TS>(h);
 
     const int KTOT = BYe + 2 * R * T + T;
@@ -416,12 +426,8 @@ __device__ __forceinline__ void valu2d_tile(const Valu2DJob<TC> &a,
                         Vec ov;
 #pragma unroll
                         for (int j = 0; j < W; ++j) ov.e[j] = to_storage<TS>(outv[j]);
-                        bool all = vec_ok;
-#pragma unroll
-                        for (int j = 0; j < W; ++j) all = all && col_store[j];
-                        if (all) {
-                            ov.store(rowp + cb);
-                        } else {
+                        if (st_all) ov.store(rowp + cb);
+                        if (st_part_wave && !st_all) {
 #pragma unroll
                             for (int j = 0; j < W; ++j)
                                 if (col_store[j]) rowp[cb + j] = ov.e[j];
